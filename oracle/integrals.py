@@ -1,0 +1,175 @@
+"""Real-space quadratures on the atom-centred grid (oracle, plain FP64 numpy).
+
+* Hamiltonian matrix, eq. (H_int_aims) restricted to a local potential:
+      h_ij = sum_p w_p v_p phi_i(r_p) phi_j(r_p)
+  (the operator acting on phi_j is taken to be multiplication by v_eff(r);
+  the kinetic part is not part of this path).
+* Overlap matrix, eq. (OverlapNoPeriodic) on the same grid: v = 1.
+* Density, eq. (Density): n(r_p) = sum_ij phi_i(r_p) n_ij phi_j(r_p).  The
+  density matrix is symmetric; like the symmetric matrix product the paper
+  uses for it (Section "GPGPU Acceleration of the RSDD Algorithm"), only its
+  upper triangle (i <= j) is read and the lower one is taken as its mirror.
+* Electron count N_e = sum_p w_p n(r_p).
+
+The point sums are split over a uniform cell grid of edge 1.5 Angstrom (at
+most 4096 points per piece) purely to bound memory; every piece adds its
+full contribution, restricted to the atoms with a point inside their cutoff
+sphere (all others contribute exact zeros).  The cells are independent of the
+octree batches.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .batching import relevant_atoms_of_points
+
+CELL_EDGE = 1.5
+CELL_CAP = 4096
+
+
+def symmetric_from_upper(D) -> np.ndarray:
+    """The symmetric matrix whose upper triangle (i <= j) is that of D."""
+    D = np.asarray(D, dtype=np.float64)
+    U = np.triu(D)
+    return U + np.triu(D, 1).T
+
+
+def cell_chunks(xyz, edge: float = CELL_EDGE, cap: int = CELL_CAP):
+    """Point index arrays, one per (cell, piece of at most cap points)."""
+    xyz = np.asarray(xyz, dtype=np.float64).reshape(-1, 3)
+    if len(xyz) == 0:
+        return []
+    c = np.floor((xyz - xyz.min(axis=0)) / edge).astype(np.int64)
+    dims = c.max(axis=0) + 1
+    key = (c[:, 2] * dims[1] + c[:, 1]) * dims[0] + c[:, 0]
+    order = np.argsort(key, kind="stable")
+    ks = key[order]
+    cuts = np.nonzero(np.diff(ks))[0] + 1
+    out = []
+    for cell in np.split(order, cuts):
+        for s in range(0, len(cell), cap):
+            out.append(cell[s:s + cap])
+    return out
+
+
+def hamiltonian(basis, xyz, w, v, chunks=None) -> np.ndarray:
+    """h_ij = sum_p w_p v_p phi_i(r_p) phi_j(r_p), symmetrised as (H + H^T)/2."""
+    xyz = np.asarray(xyz, dtype=np.float64).reshape(-1, 3)
+    wv = np.asarray(w, dtype=np.float64) * np.asarray(v, dtype=np.float64)
+    H = np.zeros((basis.n_basis, basis.n_basis))
+    for idx in (chunks if chunks is not None else cell_chunks(xyz)):
+        atoms = relevant_atoms_of_points(xyz[idx], basis.atom_xyz, basis.atom_rcut)
+        if len(atoms) == 0:
+            continue
+        fns = basis.functions_of(atoms)
+        Phi = basis.phi(xyz[idx], atoms)
+        H[np.ix_(fns, fns)] += Phi.T @ (wv[idx][:, None] * Phi)
+    return 0.5 * (H + H.T)
+
+
+def overlap(basis, xyz, w, chunks=None) -> np.ndarray:
+    """s_ij on the grid: the v = 1 case of the Hamiltonian quadrature."""
+    return hamiltonian(basis, xyz, w, np.ones(len(w)), chunks)
+
+
+def density(basis, xyz, D, chunks=None) -> np.ndarray:
+    """n(r_p) = sum_ij phi_i(r_p) D_ij phi_j(r_p) for every point (caller order)."""
+    xyz = np.asarray(xyz, dtype=np.float64).reshape(-1, 3)
+    Ds = symmetric_from_upper(D)
+    n = np.zeros(len(xyz))
+    for idx in (chunks if chunks is not None else cell_chunks(xyz)):
+        atoms = relevant_atoms_of_points(xyz[idx], basis.atom_xyz, basis.atom_rcut)
+        if len(atoms) == 0:
+            continue
+        fns = basis.functions_of(atoms)
+        Phi = basis.phi(xyz[idx], atoms)
+        T = Phi @ Ds[np.ix_(fns, fns)]
+        n[idx] = (T * Phi).sum(axis=1)
+    return n
+
+
+def electron_count(w, n) -> float:
+    """N_e = sum_p w_p n(r_p)."""
+    return float(np.dot(np.asarray(w, dtype=np.float64), np.asarray(n, dtype=np.float64)))
+
+
+def density_at(basis, pts, D) -> np.ndarray:
+    """n at selected points, one point at a time (sampled checks at full size)."""
+    pts = np.asarray(pts, dtype=np.float64).reshape(-1, 3)
+    Ds = symmetric_from_upper(D)
+    out = np.zeros(len(pts))
+    for k, p in enumerate(pts):
+        atoms = relevant_atoms_of_points(p[None, :], basis.atom_xyz, basis.atom_rcut)
+        if len(atoms) == 0:
+            continue
+        fns = basis.functions_of(atoms)
+        phi = basis.phi(p[None, :], atoms)[0]
+        out[k] = phi @ Ds[np.ix_(fns, fns)] @ phi
+    return out
+
+
+def hamiltonian_entries(basis, xyz, w, v, pairs) -> np.ndarray:
+    """h_ij for selected (i, j) pairs: sum over the points inside both cutoff spheres."""
+    xyz = np.asarray(xyz, dtype=np.float64).reshape(-1, 3)
+    wv = np.asarray(w, dtype=np.float64) * np.asarray(v, dtype=np.float64)
+    out = np.zeros(len(pairs))
+    for k, (i, j) in enumerate(pairs):
+        a, b = int(basis.fn_atom[i]), int(basis.fn_atom[j])
+        sel = np.ones(len(xyz), dtype=bool)
+        for at in (a, b):
+            X = basis.atom_xyz[at]
+            dx = xyz[:, 0] - X[0]
+            dy = xyz[:, 1] - X[1]
+            dz = xyz[:, 2] - X[2]
+            sel &= ((dx * dx + dy * dy) + dz * dz) < basis.atom_rcut[at] * basis.atom_rcut[at]
+        idx = np.nonzero(sel)[0]
+        if len(idx) == 0:
+            continue
+        pa = basis.phi_atom(xyz[idx], a)[:, i - basis.atom_first[a]]
+        pb = basis.phi_atom(xyz[idx], b)[:, j - basis.atom_first[b]]
+        out[k] = float(np.sum(wv[idx] * pa * pb))
+    return out
+
+
+def hamiltonian_batched(basis, xyz, w, v, perm, batch_ptr, basis_ptr, basis_idx) -> np.ndarray:
+    """eq. (H_decomp)/(H_contrib_batch): h = sum over batches of the dense batch matrices
+    K L (eq. batch_matrix_mult) restricted to each batch's list, then symmetrised."""
+    xyz = np.asarray(xyz, dtype=np.float64).reshape(-1, 3)
+    wv = np.asarray(w, dtype=np.float64) * np.asarray(v, dtype=np.float64)
+    H = np.zeros((basis.n_basis, basis.n_basis))
+    for b in range(len(batch_ptr) - 1):
+        idx = perm[batch_ptr[b]:batch_ptr[b + 1]]
+        fns = np.asarray(basis_idx[basis_ptr[b]:basis_ptr[b + 1]], dtype=np.int64)
+        if len(fns) == 0:
+            continue
+        atoms = np.unique(basis.fn_atom[fns])
+        Phi = basis.phi(xyz[idx], atoms)
+        K = (wv[idx][:, None] * Phi).T
+        H[np.ix_(fns, fns)] += K @ Phi
+    return 0.5 * (H + H.T)
+
+
+def density_batched(basis, xyz, D, perm, batch_ptr, basis_ptr, basis_idx) -> np.ndarray:
+    """n per batch through the batch density matrix n_ij[B] (Section "GPGPU Acceleration of
+    the RSDD Algorithm": reduce the full density matrix to the batch's list, then a matrix
+    product and a row-wise dot product)."""
+    xyz = np.asarray(xyz, dtype=np.float64).reshape(-1, 3)
+    Ds = symmetric_from_upper(D)
+    n = np.zeros(len(xyz))
+    for b in range(len(batch_ptr) - 1):
+        idx = perm[batch_ptr[b]:batch_ptr[b + 1]]
+        fns = np.asarray(basis_idx[basis_ptr[b]:basis_ptr[b + 1]], dtype=np.int64)
+        if len(fns) == 0:
+            continue
+        atoms = np.unique(basis.fn_atom[fns])
+        Phi = basis.phi(xyz[idx], atoms)
+        n[idx] = ((Phi @ Ds[np.ix_(fns, fns)]) * Phi).sum(axis=1)
+    return n
+
+
+def batch_phi(basis, xyz, perm, batch_ptr, basis_ptr, basis_idx, b) -> np.ndarray:
+    """The dense batch basis matrix [|B|, m] (point-major) of batch b."""
+    idx = perm[batch_ptr[b]:batch_ptr[b + 1]]
+    fns = np.asarray(basis_idx[basis_ptr[b]:basis_ptr[b + 1]], dtype=np.int64)
+    atoms = np.unique(basis.fn_atom[fns]) if len(fns) else []
+    return basis.phi(np.asarray(xyz, dtype=np.float64).reshape(-1, 3)[idx], atoms)

@@ -1,0 +1,79 @@
+"""Radial functions as natural cubic splines on a logarithmic grid (oracle).
+
+The paper's basis functions are numeric atom-centred orbitals whose radial
+parts vanish beyond a confining radius (Section "Computational Choices in
+FHI-aims"); it does not state how they are tabulated.  Reading used here:
+
+* knots r_k = rmin (rcut/rmin)^(k/(N-1)), k = 0..N-1; spline variable
+  t = ln(r/rmin)/Delta with Delta = ln(rcut/rmin)/(N-1), so knot k sits at t = k;
+* natural boundary conditions: M_0 = M_{N-1} = 0 and, for 0 < k < N-1,
+  M_{k-1} + 4 M_k + M_{k+1} = 6 (y_{k-1} - 2 y_k + y_{k+1}),
+  where M_k is the second derivative in t;
+* evaluation: R = 0 outside the cutoff; otherwise t is clamped to [0, N-1],
+  k = min(floor(t), N-2), u = t - k and
+  R = (1-u) y_k + u y_{k+1} + (((1-u)^3 - (1-u)) M_k + (u^3 - u) M_{k+1}) / 6.
+
+Plain Python loops for the tridiagonal solve (Thomas algorithm).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+
+def second_derivatives(y) -> np.ndarray:
+    """M_k of the natural cubic spline through y_k at unit-spaced t = k."""
+    y = [float(v) for v in y]
+    n = len(y)
+    if n < 4:
+        raise ValueError("need at least 4 knots")
+    m = n - 2  # unknowns M_1..M_{n-2}
+    diag = [4.0] * m
+    rhs = [6.0 * (y[k - 1] - 2.0 * y[k] + y[k + 1]) for k in range(1, n - 1)]
+    # forward elimination (sub- and super-diagonals are 1)
+    for i in range(1, m):
+        f = 1.0 / diag[i - 1]
+        diag[i] -= f
+        rhs[i] -= f * rhs[i - 1]
+    M = [0.0] * m
+    M[m - 1] = rhs[m - 1] / diag[m - 1]
+    for i in range(m - 2, -1, -1):
+        M[i] = (rhs[i] - M[i + 1]) / diag[i]
+    return np.array([0.0] + M + [0.0])
+
+
+def spline_t(r, rmin: float, rcut: float, n_knots: int) -> np.ndarray:
+    """Spline coordinate t = ln(r/rmin)/Delta, clamped to [0, N-1] (r <= rmin gives 0)."""
+    r = np.asarray(r, dtype=np.float64)
+    delta = math.log(rcut / rmin) / (n_knots - 1)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        t = np.where(r > rmin, np.log(np.where(r > rmin, r, rmin) / rmin) / delta, 0.0)
+    return np.clip(t, 0.0, float(n_knots - 1))
+
+
+def evaluate_t(t, y, M) -> np.ndarray:
+    """Cubic spline value at (already clamped) coordinate t."""
+    t = np.asarray(t, dtype=np.float64)
+    n = len(y)
+    k = np.minimum(np.floor(t).astype(np.int64), n - 2)
+    u = t - k
+    a = 1.0 - u
+    return a * y[k] + u * y[k + 1] + ((a ** 3 - a) * M[k] + (u ** 3 - u) * M[k + 1]) / 6.0
+
+
+class RadialSpline:
+    """One tabulated radial function R(r) on the logarithmic grid."""
+
+    def __init__(self, samples, rmin: float, rcut: float):
+        self.y = np.asarray(samples, dtype=np.float64)
+        self.M = second_derivatives(self.y)
+        self.rmin = float(rmin)
+        self.rcut = float(rcut)
+        self.n = len(self.y)
+
+    def at_r(self, r) -> np.ndarray:
+        """R(r) with R = 0 for r >= rcut (used by the spline pins)."""
+        r = np.asarray(r, dtype=np.float64)
+        val = evaluate_t(spline_t(r, self.rmin, self.rcut, self.n), self.y, self.M)
+        return np.where(r >= self.rcut, 0.0, val)
