@@ -1,0 +1,228 @@
+/*
+ * nao.h -- C ABI of the MI355X (gfx950) real-space grid engine for numeric
+ * atom-centred orbitals: batch-wise Hamiltonian integration and density
+ * update over spatially compact batches of integration points.
+ *
+ * Method: Huhn, Lange, Yu, Yoon, Blum, "GPGPU Acceleration of All-Electron
+ * Electronic Structure Theory Using Localized Numeric Atom-Centered Basis
+ * Functions".  Section references below are to that paper.
+ *
+ * Conventions for every call:
+ *   - all real data are FP64 (double) at the boundary, lengths are int64_t,
+ *     coordinates are in Angstrom, matrices are dense row-major N_b x N_b;
+ *   - the caller owns every buffer it passes; the library copies what it keeps;
+ *   - a nao_memspace argument says whether the pointer next to it is host
+ *     memory or device memory of the context's GPU (e.g. a torch tensor's
+ *     data_ptr()); device pointers must come from hipMalloc-type allocations;
+ *   - calls return a nao_status; no C++ exception, abort or exit crosses the
+ *     ABI; nao_last_error() returns the message of the last failing call;
+ *   - a context and its systems are used by one host thread at a time;
+ *   - work is ordered on the context's HIP stream.  A call with any host
+ *     output synchronizes before returning; a call whose outputs are all
+ *     device memory returns after enqueueing (inputs must stay valid until
+ *     the stream reaches the work).
+ *   - a HIP failure is sticky: the context reports NAO_ERR_HIP from then on.
+ */
+#ifndef NAO_H
+#define NAO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nao_ctx_s* nao_ctx;       /* one HIP device + stream + HBM-budget allocator */
+typedef struct nao_system_s* nao_system; /* one structure's resident device state          */
+typedef struct nao_plan_s* nao_plan;     /* host-only batches and lists (no GPU needed)    */
+
+typedef enum {
+    NAO_OK = 0,
+    NAO_ERR_INVALID_ARG = -1,   /* bad argument; no state was changed                     */
+    NAO_ERR_OUT_OF_MEMORY = -2, /* host or device allocation failed                       */
+    NAO_ERR_BUDGET = -3,        /* the context's HBM budget would be exceeded             */
+    NAO_ERR_HIP = -4,           /* a HIP runtime call failed; the context is now unusable */
+    NAO_ERR_NOT_READY = -5,     /* no GPU / library built without one / not initialised   */
+    NAO_ERR_INTERNAL = -6
+} nao_status;
+
+/* Arithmetic of the two contractions.  Basis evaluation, partition weights,
+ * w*v, the accumulation into the global H and the electron count are FP64 in
+ * every mode. */
+typedef enum {
+    NAO_FP64 = 0,   /* FP64 MFMA                                                       */
+    NAO_FP32 = 1,   /* FP32 MFMA, FP32 accumulation within a group, FP64 across groups */
+    NAO_BF16X3 = 2, /* three-term split-BF16 products, FP32 accumulation              */
+    NAO_BF16X6 = 3  /* six-term split-BF16 products (hi, mid, lo parts), FP32 accum.  */
+} nao_precision;
+
+typedef enum { NAO_MEM_HOST = 0, NAO_MEM_DEVICE = 1 } nao_memspace;
+
+/* ---------------------------------------------------------------------------------------
+ * Basis description: atoms with species; each species is a list of shells (l, radial id);
+ * each radial function is tabulated at n_knots logarithmic knots
+ *   r_k = rmin * (rcut/rmin)^(k/(n_knots-1)),  k = 0..n_knots-1,
+ * and is interpolated by a natural cubic spline in t = ln(r/rmin)/Delta,
+ * Delta = ln(rcut/rmin)/(n_knots-1); it is zero at and beyond rcut.  The basis function
+ *   phi(r) = R(|r - R_A|) * Y_lm(unit(r - R_A))
+ * uses real orthonormal spherical harmonics (Y_11 proportional to +x), m = -l..l.  The
+ * global basis order is atom-major, then the species' shell order, then m = -l..l.
+ * (Section "Computational Choices in FHI-aims": numeric atom-centred orbitals confined
+ * to a cutoff radius; eq. EVNonPeriodic: the basis expansion.)
+ * Constraints: 0 <= l <= 3, n_knots >= 4, 0 < rmin < rcut, finite samples.
+ * ------------------------------------------------------------------------------------- */
+typedef struct {
+    int64_t n_atoms;
+    const double* atom_xyz;           /* [n_atoms][3]                                  */
+    const int32_t* atom_species;      /* [n_atoms], 0..n_species-1                     */
+    int32_t n_species;
+    const int32_t* species_shell_ptr; /* [n_species+1], into shell_l / shell_radial     */
+    const int32_t* shell_l;           /* [n_shells], 0..3                               */
+    const int32_t* shell_radial;      /* [n_shells], 0..n_radial-1                      */
+    int32_t n_radial;
+    int32_t n_knots;
+    const double* radial_rmin;        /* [n_radial] first knot                          */
+    const double* radial_rcut;        /* [n_radial] last knot = cutoff                  */
+    const double* radial_samples;     /* [n_radial][n_knots] R(r_k)                     */
+} nao_basis_desc;
+
+/* ---------------------------------------------------------------------------------------
+ * Context.
+ * nao_ctx_create: device = HIP ordinal; hip_stream = a hipStream_t to order work on, or
+ * NULL for a stream the context creates; hbm_budget_bytes = cap on the device memory the
+ * context allocates for all its systems (0 = no cap).  NAO_ERR_NOT_READY without a GPU.
+ * ------------------------------------------------------------------------------------- */
+nao_status nao_ctx_create(int device, void* hip_stream, size_t hbm_budget_bytes, nao_ctx* out);
+void nao_ctx_destroy(nao_ctx ctx);
+/* Message of the last failing call on ctx; ctx = NULL gives the calling thread's last
+ * message of a context-less call (nao_plan_*).  Never NULL; valid until the next call. */
+const char* nao_last_error(nao_ctx ctx);
+nao_status nao_ctx_set_stream(nao_ctx ctx, void* hip_stream);
+void* nao_ctx_stream(nao_ctx ctx);
+nao_status nao_ctx_synchronize(nao_ctx ctx);
+/* Bytes currently allocated by the context and its budget (0 = none). */
+nao_status nao_ctx_memory(nao_ctx ctx, size_t* used_bytes, size_t* budget_bytes);
+
+/* Per-kernel timing (the per-operation timings the paper reports, at kernel granularity).
+ * nao_ctx_profile(ctx, 1) starts recording: every kernel launch of the context is then
+ * bracketed by HIP events on the context stream; (ctx, 0) stops.  Starting also clears
+ * what was recorded.  nao_ctx_profile_read synchronizes the stream and reports, per kernel
+ * name (at most max_entries, names as 32-byte NUL-terminated strings in names), the number
+ * of launches and their summed duration in milliseconds; n_entries receives the count. */
+nao_status nao_ctx_profile(nao_ctx ctx, int enable);
+nao_status nao_ctx_profile_read(nao_ctx ctx, int32_t max_entries, char* names, int64_t* launches,
+                                double* total_ms, int32_t* n_entries);
+
+/* ---------------------------------------------------------------------------------------
+ * Host-only planning (runs without a GPU).  Partitions the points into batches of at most
+ * max_batch points by an octree and builds each batch's list nnz(B) of basis functions
+ * that are non-zero on at least one of its points.
+ * (Section "Grid Partitioning": disjoint compact batches up to a batch size; Section
+ * "Parallelization and Dimensionality Reduction": the reduced subspace nnz(B_nu).)
+ * Octree: root box = per-axis [min, max] of all points; a node with <= max_batch points
+ * is a batch; otherwise mid = 0.5*(lo+hi), octant c = [x>=mid_x] + 2[y>=mid_y] +
+ * 4[z>=mid_z], children visited c = 0..7 depth-first pre-order, empty ones dropped,
+ * indices ascending; a node at depth >= 60, or whose mid equals lo or hi on all three
+ * axes, is cut into consecutive chunks of max_batch.  Batches are numbered in emission
+ * order.  Relevance: atom A is relevant to batch b iff some point of b has
+ * (dx*dx + dy*dy) + dz*dz < rcA*rcA in FP64 without fused multiply-add, rcA being the
+ * largest cutoff of A's radial functions; the list is the relevant atoms ascending, each
+ * expanded to its basis functions in global order.  The result is bit-exact: a fixed
+ * input gives fixed perm / batch_ptr / basis_ptr / basis_idx on every machine.
+ * max_batch in [1, 4096]; n_points in [0, 2^31-1]; point_xyz finite.
+ * ------------------------------------------------------------------------------------- */
+nao_status nao_plan_create(const nao_basis_desc* basis, int64_t n_points, const double* point_xyz,
+                           int32_t max_batch, nao_plan* out);
+nao_status nao_plan_info(nao_plan plan, int64_t* n_basis, int64_t* n_batches, int64_t* n_list);
+/* perm [n_points] (batch b = points perm[batch_ptr[b] .. batch_ptr[b+1]-1]),
+ * batch_ptr [n_batches+1], basis_ptr [n_batches+1], basis_idx [n_list]; any may be NULL. */
+nao_status nao_plan_get_batches(nao_plan plan, int64_t* perm, int64_t* batch_ptr,
+                                int64_t* basis_ptr, int32_t* basis_idx);
+void nao_plan_destroy(nao_plan plan);
+
+/* ---------------------------------------------------------------------------------------
+ * Structure setup: plans the batches (as nao_plan_create), builds the spline coefficients
+ * (FP64, on the host), packs consecutive batches into execution groups of at most
+ * group_max points (default 256; a batch larger than that is cut into pieces; exact,
+ * since every basis function is zero on the points outside its list) and uploads
+ * atoms, splines, batch-ordered points and weights, lists and groups to device memory
+ * owned by the returned system.  point_xyz [n_points][3] and point_w [n_points] are host
+ * arrays in the caller's point order; w >= 0 and finite.
+ * ------------------------------------------------------------------------------------- */
+nao_status nao_build_batches(nao_ctx ctx, const nao_basis_desc* basis, int64_t n_points,
+                             const double* point_xyz, const double* point_w, int32_t max_batch,
+                             nao_system* out);
+/* Change the execution-group size (in points, 16..1024) of a system; results change only
+ * by floating-point summation order. */
+nao_status nao_system_set_group_max(nao_system sys, int32_t group_max);
+nao_status nao_system_info(nao_system sys, int64_t* n_basis, int64_t* n_batches, int64_t* n_list,
+                           size_t* dev_bytes);
+/* Host copies of the system's batches and lists (as nao_plan_get_batches). */
+nao_status nao_get_batches(nao_system sys, int64_t* perm, int64_t* batch_ptr, int64_t* basis_ptr,
+                           int32_t* basis_idx);
+/* Work measure of the paper's "#ops" metric (Section "GPGPU Acceleration Across Materials
+ * and Architectures"): units = sum over batches of |B| * m^2 with m = |nnz(B)|. */
+nao_status nao_system_work(nao_system sys, double* units);
+
+/* ---------------------------------------------------------------------------------------
+ * Basis values phi_i(r_p) for the batches [batch_begin, batch_end): for each batch a dense
+ * [|B|][m] block, point-major, rows in batch point order, columns in list order; blocks
+ * are concatenated, block b starting at phi + phi_ptr[b - batch_begin].  phi_ptr is a host
+ * array of batch_end - batch_begin + 1 entries, always written.  phi = NULL only fills
+ * phi_ptr (size query).  (Section "GPGPU Acceleration of the RSDD Algorithm": the basis
+ * functions in nnz(B) on every point of the batch.)
+ * ------------------------------------------------------------------------------------- */
+nao_status nao_eval_basis(nao_system sys, int64_t batch_begin, int64_t batch_end, double* phi,
+                          nao_memspace phi_space, int64_t* phi_ptr);
+
+/* ---------------------------------------------------------------------------------------
+ * Hamiltonian matrix with a local potential,
+ *   H_ij = sum_p w_p v_p phi_i(r_p) phi_j(r_p),
+ * summed batch by batch through each batch's dense matrix (eq. H_int_aims, eq. H_decomp,
+ * eq. H_contrib_batch, eq. batch_matrix_mult with K = w phi and L = v phi).
+ * v [n_points] in caller point order; H [N_b][N_b] row-major, written in full and exactly
+ * symmetric (the upper triangle is accumulated, then mirrored).  With H in device memory
+ * the call only enqueues.
+ * ------------------------------------------------------------------------------------- */
+nao_status nao_integrate_h(nao_system sys, const double* v, nao_memspace v_space,
+                           nao_precision precision, double* H, nao_memspace H_space);
+
+/* ---------------------------------------------------------------------------------------
+ * Density n(r_p) = sum_ij phi_i(r_p) D_ij phi_j(r_p) at every point (eq. Density), batch by
+ * batch through the batch density matrix D[nnz(B), nnz(B)] (Section "GPGPU Acceleration
+ * of the RSDD Algorithm").  D [N_b][N_b] row-major is symmetric; like the symmetric
+ * matrix product used for it in the paper, only its upper triangle (i <= j) is read.
+ * n [n_points] in caller point order (exact zeros where no basis function reaches).
+ * n_electrons (host, nullable) receives N_e = sum_p w_p n_p; passing it synchronizes.
+ * ------------------------------------------------------------------------------------- */
+nao_status nao_update_density(nao_system sys, const double* D, nao_memspace D_space,
+                              nao_precision precision, double* n, nao_memspace n_space,
+                              double* n_electrons);
+void nao_system_destroy(nao_system sys);
+
+/* ---------------------------------------------------------------------------------------
+ * Many structures in one launch sequence: the work of every entry (op 0 = H with in = v,
+ * out = H; op 1 = density with in = D, out = n) is packed into one work list per kernel
+ * and launched together.  All pointers are device memory of the context's device; every
+ * system must belong to ctx.  NAO_RUN_CAPTURE_GRAPH records the sequence into a HIP graph
+ * on first use and replays it while the (systems, pointers, precision) tuple repeats.
+ * n_electrons must be NULL here (use nao_update_density for it).
+ * ------------------------------------------------------------------------------------- */
+typedef struct {
+    nao_system sys;
+    int32_t op;         /* 0 = Hamiltonian, 1 = density */
+    const double* in;   /* v [n_points] or D [N_b][N_b] */
+    double* out;        /* H [N_b][N_b] or n [n_points] */
+} nao_work;
+
+#define NAO_RUN_CAPTURE_GRAPH 1u
+
+nao_status nao_run_many(nao_ctx ctx, const nao_work* work, int64_t n_work, nao_precision precision,
+                        uint32_t flags);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NAO_H */

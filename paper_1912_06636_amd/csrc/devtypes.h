@@ -1,0 +1,96 @@
+// Types shared by the host runtime (runtime.cpp) and the kernels (kernels.hip).
+#pragma once
+
+#include <cstdint>
+
+#include <hip/hip_runtime_api.h>
+
+namespace nao {
+
+constexpr int TILE = 64;              // basis-function tile of the contraction kernels
+constexpr int KCHUNK = 16;            // points (Hamiltonian) / functions (density) per LDS stage
+constexpr int MAX_UNIT_POINTS = 256;  // largest execution group the contraction kernels take
+constexpr int MAX_SPLINE_LDS = 8192;  // doubles of spline table staged in LDS (64 KiB)
+
+// One structure's resident device state, as seen by the kernels.
+struct DevSys {
+    const double* px;                  // batch-ordered point coordinates [n_points]
+    const double* py;
+    const double* pz;
+    const double* pw;                  // batch-ordered weights
+    const int32_t* perm;               // batch order -> caller index
+    const double* atom_xyzr;           // [n_atoms][4]: x, y, z, (largest cutoff)^2
+    const int32_t* atom_species;       // [n_atoms]
+    const int32_t* species_shell_ptr;  // [n_species+1]
+    const int32_t* shell_l;            // [n_shells]
+    const int32_t* shell_radial;       // [n_shells]
+    const double* radial_par;          // [n_radial][4]: rmin, rcut^2, 1/Delta, ln(rmin)
+    const double* spline;              // [n_radial][n_knots-1][4] polynomial coefficients
+    int32_t n_radial;
+    int32_t n_knots;
+    int64_t n_basis;
+    int64_t n_points;
+};
+
+// A run of batch-ordered points evaluated against one list of atoms.
+struct DevUnit {
+    int64_t point_begin;  // into the system's batch-ordered points
+    int64_t atom_begin;   // into unit_atoms / unit_cols
+    int64_t fn_begin;     // into unit_fn (global basis index of every column)
+    int64_t out_offset;   // element offset of this unit's [n_points][ld] block within its block
+    int32_t n_points;
+    int32_t n_atoms;
+    int32_t m;            // columns in use
+    int32_t ld;           // row stride of the basis block (>= m)
+};
+
+// Work item of the Hamiltonian kernel: one tile pair (ti <= tj) of one unit.
+struct HItem {
+    int32_t unit;  // index into the system's unit array
+    int16_t ti;
+    int16_t tj;
+};
+
+// Work item of the density kernel: one column tile of one unit.
+struct NItem {
+    int32_t unit;
+    int32_t tj;
+};
+
+// One segment of a launch: a block of one system's units (and their work items) whose
+// basis values live at phi.  A launch covers a list of segments; block b of a launch maps
+// to the segment whose prefix range contains it.
+struct DevSeg {
+    const DevSys* sys;
+    const DevUnit* units;
+    const int32_t* unit_atoms;
+    const int32_t* unit_cols;
+    const int32_t* unit_fn;
+    const void* items;       // HItem* or NItem*
+    double* phi;             // basis values of this block (unit.out_offset is relative to it)
+    const double* wv;        // batch-ordered w*v (Hamiltonian)
+    const double* D;         // density matrix (density), row-major, ld = n_basis
+    double* H;               // Hamiltonian, row-major, ld = n_basis
+    double* n;               // density, caller order
+    int64_t ld;              // n_basis
+    int64_t unit_begin, unit_count, unit_prefix;
+    int64_t item_begin, item_count, item_prefix;
+};
+
+// ------------------------------------------------------------------------------------------
+// kernel launchers (kernels.hip).  Every launcher checks its own grid against the segment
+// table before launching and returns hipErrorInvalidValue on a mismatch.
+
+hipError_t launch_basis_f64(const DevSeg* segs_dev, int n_segs, int64_t n_units, bool spline_in_lds,
+                            hipStream_t st);
+hipError_t launch_h_f64(const DevSeg* segs_dev, int n_segs, int64_t n_items, hipStream_t st);
+hipError_t launch_n_f64(const DevSeg* segs_dev, int n_segs, int64_t n_items, hipStream_t st);
+hipError_t launch_fill(double* p, int64_t n, double value, hipStream_t st);
+hipError_t launch_wv(const double* pw, const int32_t* perm, const double* v_caller, double* wv,
+                     int64_t n_points, hipStream_t st);
+hipError_t launch_mirror(double* H, int64_t n, hipStream_t st);
+hipError_t launch_weighted_sum(const double* pw, const int32_t* perm, const double* n_caller,
+                               int64_t n_points, double* partial, double* out, hipStream_t st);
+constexpr int WSUM_BLOCKS = 1024;
+
+}  // namespace nao

@@ -1,0 +1,992 @@
+// Host runtime behind the C ABI (nao.h): contexts with an HBM budget, resident systems,
+// execution groups and blocks, and the launch sequences of the API calls.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include <hip/hip_runtime_api.h>
+
+#include "devtypes.h"
+#include "nao.h"
+#include "plan.h"
+
+using namespace nao;
+
+namespace {
+
+thread_local std::string g_thread_error;
+
+struct Fail {
+    nao_status st;
+    std::string msg;
+};
+
+}  // namespace
+
+// ------------------------------------------------------------------------------------------
+// context
+
+struct nao_ctx_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    size_t budget = 0;
+    size_t used = 0;
+    bool failed = false;
+    std::string err;
+    double* scratch = nullptr;   // basis values of one block of units
+    size_t scratch_elems = 0;
+    size_t scratch_cap_elems = 0;
+    double* wsum = nullptr;      // WSUM_BLOCKS partials + 1 result
+    int n_systems = 0;
+    // per-kernel timing
+    bool prof = false;
+    struct Rec {
+        const char* name;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+};
+
+namespace {
+
+void set_err(nao_ctx c, const std::string& m)
+{
+    if (c) c->err = m;
+    g_thread_error = m;
+}
+
+nao_status hip_fail(nao_ctx c, hipError_t e, const char* what)
+{
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    if (c) c->failed = true;
+    set_err(c, m);
+    return NAO_ERR_HIP;
+}
+
+#define HIP_TRY(ctx, expr)                                   \
+    do {                                                     \
+        hipError_t e__ = (expr);                             \
+        if (e__ != hipSuccess) return hip_fail(ctx, e__, #expr); \
+    } while (0)
+
+hipEvent_t take_event(nao_ctx c)
+{
+    if (!c->pool.empty()) {
+        hipEvent_t e = c->pool.back();
+        c->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Launch through f(); when profiling, bracket it with events on the context stream.
+template <typename F>
+hipError_t timed(nao_ctx c, const char* name, F&& f)
+{
+    if (!c->prof) return f();
+    hipEvent_t a = take_event(c), b = take_event(c);
+    if (!a || !b) return hipErrorOutOfMemory;
+    hipError_t e = hipEventRecord(a, c->stream);
+    if (e != hipSuccess) return e;
+    e = f();
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(b, c->stream);
+    c->recs.push_back({name, a, b});
+    return e;
+}
+
+#define LAUNCH(ctx, name, call) HIP_TRY(ctx, timed(ctx, name, [&]() { return (call); }))
+
+nao_status dev_alloc(nao_ctx c, size_t bytes, void** out)
+{
+    *out = nullptr;
+    if (bytes == 0) return NAO_OK;
+    if (c->budget && c->used + bytes > c->budget) {
+        set_err(c, "HBM budget exceeded: need " + std::to_string(bytes) + " B, used " + std::to_string(c->used) +
+                       " of " + std::to_string(c->budget));
+        return NAO_ERR_BUDGET;
+    }
+    hipError_t e = hipMalloc(out, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *out = nullptr;
+        set_err(c, std::string("hipMalloc of ") + std::to_string(bytes) + " B failed: " + hipGetErrorString(e));
+        return NAO_ERR_OUT_OF_MEMORY;
+    }
+    c->used += bytes;
+    return NAO_OK;
+}
+
+void dev_free(nao_ctx c, void* p, size_t bytes)
+{
+    if (!p) return;
+    (void)hipFree(p);
+    c->used -= std::min(c->used, bytes);
+}
+
+struct DevArray {
+    void* p = nullptr;
+    size_t bytes = 0;
+    template <typename T> T* as() const { return static_cast<T*>(p); }
+};
+
+nao_status upload(nao_ctx c, DevArray& a, const void* src, size_t bytes)
+{
+    if (a.bytes != bytes) {
+        dev_free(c, a.p, a.bytes);
+        a.p = nullptr;
+        a.bytes = 0;
+        nao_status s = dev_alloc(c, bytes, &a.p);
+        if (s != NAO_OK) return s;
+        a.bytes = bytes;
+    }
+    if (bytes) HIP_TRY(c, hipMemcpyAsync(a.p, src, bytes, hipMemcpyHostToDevice, c->stream));
+    return NAO_OK;
+}
+
+nao_status ensure(nao_ctx c, DevArray& a, size_t bytes)
+{
+    if (a.bytes >= bytes && a.p) return NAO_OK;
+    dev_free(c, a.p, a.bytes);
+    a.p = nullptr;
+    a.bytes = 0;
+    nao_status s = dev_alloc(c, bytes, &a.p);
+    if (s == NAO_OK) a.bytes = bytes;
+    return s;
+}
+
+nao_status check_ctx(nao_ctx c)
+{
+    if (!c) {
+        g_thread_error = "context is NULL";
+        return NAO_ERR_INVALID_ARG;
+    }
+    if (c->failed) {
+        set_err(c, "context is unusable after an earlier HIP failure: " + c->err);
+        return NAO_ERR_HIP;
+    }
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+    return NAO_OK;
+}
+
+size_t scratch_cap_from_env()
+{
+    size_t mb = 2048;
+    if (const char* s = std::getenv("NAO_SCRATCH_MB")) {
+        long v = std::atol(s);
+        if (v >= 16) mb = (size_t)v;
+    }
+    return mb * (size_t)1024 * 1024 / sizeof(double);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------------------------
+// system
+
+namespace {
+
+struct Block {
+    int64_t unit_begin = 0, unit_count = 0;
+    int64_t h_begin = 0, h_count = 0;
+    int64_t n_begin = 0, n_count = 0;
+    int64_t phi_elems = 0;
+};
+
+}  // namespace
+
+struct nao_system_s {
+    nao_ctx ctx = nullptr;
+    HostBasis basis;
+    int64_t n_points = 0;
+    int32_t max_batch = 0;
+    int32_t group_max = MAX_UNIT_POINTS;
+    std::vector<int64_t> perm, batch_ptr, atom_ptr;
+    std::vector<int32_t> atoms;
+    double work_units = 0.0;
+    // groups
+    std::vector<Block> blocks;
+    int64_t n_units = 0, n_h_items = 0, n_n_items = 0;
+    // device state
+    DevSys dsys{};
+    DevArray d_sys, d_px, d_py, d_pz, d_pw, d_perm, d_atoms, d_species, d_shell_ptr, d_shell_l, d_shell_rad,
+        d_radial_par, d_spline;
+    DevArray d_units, d_unit_atoms, d_unit_cols, d_unit_fn, d_h_items, d_n_items;
+    DevArray d_wv, d_v, d_D, d_H, d_n, d_segs;
+    bool spline_lds = true;
+};
+
+namespace {
+
+size_t system_bytes(const nao_system_s* s)
+{
+    const DevArray* arr[] = {&s->d_sys, &s->d_px, &s->d_py, &s->d_pz, &s->d_pw, &s->d_perm, &s->d_atoms,
+                             &s->d_species, &s->d_shell_ptr, &s->d_shell_l, &s->d_shell_rad, &s->d_radial_par,
+                             &s->d_spline, &s->d_units, &s->d_unit_atoms, &s->d_unit_cols, &s->d_unit_fn,
+                             &s->d_h_items, &s->d_n_items, &s->d_wv, &s->d_v, &s->d_D, &s->d_H, &s->d_n,
+                             &s->d_segs};
+    size_t t = 0;
+    for (auto* a : arr) t += a->bytes;
+    return t;
+}
+
+void free_all(nao_system_s* s)
+{
+    DevArray* arr[] = {&s->d_sys, &s->d_px, &s->d_py, &s->d_pz, &s->d_pw, &s->d_perm, &s->d_atoms,
+                       &s->d_species, &s->d_shell_ptr, &s->d_shell_l, &s->d_shell_rad, &s->d_radial_par,
+                       &s->d_spline, &s->d_units, &s->d_unit_atoms, &s->d_unit_cols, &s->d_unit_fn,
+                       &s->d_h_items, &s->d_n_items, &s->d_wv, &s->d_v, &s->d_D, &s->d_H, &s->d_n, &s->d_segs};
+    for (auto* a : arr) {
+        dev_free(s->ctx, a->p, a->bytes);
+        a->p = nullptr;
+        a->bytes = 0;
+    }
+}
+
+int32_t round_up(int32_t x, int32_t m) { return (x + m - 1) / m * m; }
+
+// Build execution groups, split them into scratch-sized blocks and upload units and items.
+nao_status build_groups(nao_system_s* s)
+{
+    nao_ctx c = s->ctx;
+    std::vector<Unit> units;
+    std::vector<int32_t> uat, ucol;
+    make_groups(s->basis, s->batch_ptr, s->atom_ptr, s->atoms, s->group_max, units, uat, ucol);
+    std::vector<DevUnit> du(units.size());
+    std::vector<int32_t> ufn;
+    std::vector<HItem> hitems;
+    std::vector<NItem> nitems;
+    s->blocks.clear();
+    Block cur;
+    int64_t off = 0;
+    const int64_t cap = (int64_t)c->scratch_cap_elems;
+    for (size_t k = 0; k < units.size(); ++k) {
+        const Unit& u = units[k];
+        DevUnit& d = du[k];
+        d.point_begin = u.point_begin;
+        d.atom_begin = u.atom_begin;
+        d.fn_begin = (int64_t)ufn.size();
+        d.n_points = u.n_points;
+        d.n_atoms = u.n_atoms;
+        d.m = u.m;
+        d.ld = round_up(u.m, TILE);
+        for (int32_t q = 0; q < u.n_atoms; ++q) {
+            const int32_t a = uat[u.atom_begin + q];
+            for (int64_t f = s->basis.atom_first[a]; f < s->basis.atom_first[a + 1]; ++f) ufn.push_back((int32_t)f);
+        }
+        const int64_t elems = (int64_t)d.n_points * d.ld;
+        if (elems > cap) return (set_err(c, "one execution group exceeds the scratch size"), NAO_ERR_INTERNAL);
+        if (off + elems > cap) {
+            s->blocks.push_back(cur);
+            cur = Block();
+            cur.unit_begin = (int64_t)k;
+            cur.h_begin = (int64_t)hitems.size();
+            cur.n_begin = (int64_t)nitems.size();
+            off = 0;
+        }
+        d.out_offset = off;
+        off += elems;
+        cur.phi_elems = off;
+        cur.unit_count++;
+        const int nt = d.ld / TILE;
+        for (int tj = 0; tj < nt; ++tj) {
+            for (int ti = 0; ti <= tj; ++ti) hitems.push_back(HItem{(int32_t)k, (int16_t)ti, (int16_t)tj});
+            nitems.push_back(NItem{(int32_t)k, tj});
+        }
+        cur.h_count = (int64_t)hitems.size() - cur.h_begin;
+        cur.n_count = (int64_t)nitems.size() - cur.n_begin;
+    }
+    if (cur.unit_count) s->blocks.push_back(cur);
+    s->n_units = (int64_t)units.size();
+    s->n_h_items = (int64_t)hitems.size();
+    s->n_n_items = (int64_t)nitems.size();
+    if (hitems.size() > 0x7fffffffu) return (set_err(c, "too many work items"), NAO_ERR_INTERNAL);
+    nao_status st;
+    if ((st = upload(c, s->d_units, du.data(), du.size() * sizeof(DevUnit))) != NAO_OK) return st;
+    if ((st = upload(c, s->d_unit_atoms, uat.data(), uat.size() * sizeof(int32_t))) != NAO_OK) return st;
+    if ((st = upload(c, s->d_unit_cols, ucol.data(), ucol.size() * sizeof(int32_t))) != NAO_OK) return st;
+    if ((st = upload(c, s->d_unit_fn, ufn.data(), ufn.size() * sizeof(int32_t))) != NAO_OK) return st;
+    if ((st = upload(c, s->d_h_items, hitems.data(), hitems.size() * sizeof(HItem))) != NAO_OK) return st;
+    if ((st = upload(c, s->d_n_items, nitems.data(), nitems.size() * sizeof(NItem))) != NAO_OK) return st;
+    if ((st = ensure(c, s->d_segs, std::max<size_t>(1, s->blocks.size()) * sizeof(DevSeg))) != NAO_OK) return st;
+    size_t need = 0;
+    for (const Block& b : s->blocks) need = std::max(need, (size_t)b.phi_elems);
+    if (need > c->scratch_elems) {
+        dev_free(c, c->scratch, c->scratch_elems * sizeof(double));
+        c->scratch = nullptr;
+        c->scratch_elems = 0;
+        void* p = nullptr;
+        if ((st = dev_alloc(c, need * sizeof(double), &p)) != NAO_OK) return st;
+        c->scratch = static_cast<double*>(p);
+        c->scratch_elems = need;
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return NAO_OK;
+}
+
+DevSeg make_seg(const nao_system_s* s, const Block& b, bool ham)
+{
+    DevSeg g{};
+    g.sys = s->d_sys.as<DevSys>();
+    g.units = s->d_units.as<DevUnit>();
+    g.unit_atoms = s->d_unit_atoms.as<int32_t>();
+    g.unit_cols = s->d_unit_cols.as<int32_t>();
+    g.unit_fn = s->d_unit_fn.as<int32_t>();
+    g.items = ham ? (const void*)s->d_h_items.p : (const void*)s->d_n_items.p;
+    g.phi = s->ctx->scratch;
+    g.ld = s->basis.n_basis;
+    g.unit_begin = b.unit_begin;
+    g.unit_count = b.unit_count;
+    g.unit_prefix = 0;
+    g.item_begin = ham ? b.h_begin : b.n_begin;
+    g.item_count = ham ? b.h_count : b.n_count;
+    g.item_prefix = 0;
+    return g;
+}
+
+bool finite_all(const double* p, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------------------------
+// C ABI
+
+extern "C" {
+
+nao_status nao_ctx_create(int device, void* hip_stream, size_t hbm_budget_bytes, nao_ctx* out)
+{
+    if (!out) {
+        g_thread_error = "out is NULL";
+        return NAO_ERR_INVALID_ARG;
+    }
+    *out = nullptr;
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count <= 0) {
+        (void)hipGetLastError();
+        g_thread_error = "no HIP device available";
+        return NAO_ERR_NOT_READY;
+    }
+    if (device < 0 || device >= count) {
+        g_thread_error = "device ordinal out of range";
+        return NAO_ERR_INVALID_ARG;
+    }
+    nao_ctx c = new (std::nothrow) nao_ctx_s();
+    if (!c) return NAO_ERR_OUT_OF_MEMORY;
+    c->device = device;
+    c->budget = hbm_budget_bytes;
+    c->scratch_cap_elems = scratch_cap_from_env();
+    e = hipSetDevice(device);
+    if (e == hipSuccess) {
+        if (hip_stream) {
+            c->stream = static_cast<hipStream_t>(hip_stream);
+        } else {
+            e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+            c->own_stream = e == hipSuccess;
+        }
+    }
+    if (e == hipSuccess) {
+        void* p = nullptr;
+        nao_status s = dev_alloc(c, (WSUM_BLOCKS + 1) * sizeof(double), &p);
+        if (s != NAO_OK) {
+            g_thread_error = c->err;
+            if (c->own_stream) (void)hipStreamDestroy(c->stream);
+            delete c;
+            return s;
+        }
+        c->wsum = static_cast<double*>(p);
+    }
+    if (e != hipSuccess) {
+        g_thread_error = std::string("context setup failed: ") + hipGetErrorString(e);
+        delete c;
+        return NAO_ERR_HIP;
+    }
+    *out = c;
+    return NAO_OK;
+}
+
+void nao_ctx_destroy(nao_ctx c)
+{
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    dev_free(c, c->scratch, c->scratch_elems * sizeof(double));
+    dev_free(c, c->wsum, (WSUM_BLOCKS + 1) * sizeof(double));
+    for (auto& r : c->recs) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (auto e : c->pool) (void)hipEventDestroy(e);
+    if (c->own_stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+const char* nao_last_error(nao_ctx c)
+{
+    if (c) return c->err.c_str();
+    return g_thread_error.c_str();
+}
+
+nao_status nao_ctx_set_stream(nao_ctx c, void* hip_stream)
+{
+    nao_status st = check_ctx(c);
+    if (st != NAO_OK) return st;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (c->own_stream) HIP_TRY(c, hipStreamDestroy(c->stream));
+    c->own_stream = false;
+    if (hip_stream) {
+        c->stream = static_cast<hipStream_t>(hip_stream);
+    } else {
+        HIP_TRY(c, hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+        c->own_stream = true;
+    }
+    return NAO_OK;
+}
+
+void* nao_ctx_stream(nao_ctx c) { return c ? (void*)c->stream : nullptr; }
+
+nao_status nao_ctx_synchronize(nao_ctx c)
+{
+    nao_status st = check_ctx(c);
+    if (st != NAO_OK) return st;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return NAO_OK;
+}
+
+nao_status nao_ctx_memory(nao_ctx c, size_t* used, size_t* budget)
+{
+    if (!c) {
+        g_thread_error = "context is NULL";
+        return NAO_ERR_INVALID_ARG;
+    }
+    if (used) *used = c->used;
+    if (budget) *budget = c->budget;
+    return NAO_OK;
+}
+
+nao_status nao_ctx_profile(nao_ctx c, int enable)
+{
+    nao_status st = check_ctx(c);
+    if (st != NAO_OK) return st;
+    if (enable) {
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        for (auto& r : c->recs) {
+            c->pool.push_back(r.a);
+            c->pool.push_back(r.b);
+        }
+        c->recs.clear();
+    }
+    c->prof = enable != 0;
+    return NAO_OK;
+}
+
+nao_status nao_ctx_profile_read(nao_ctx c, int32_t max_entries, char* names, int64_t* launches, double* total_ms,
+                                int32_t* n_entries)
+{
+    nao_status st = check_ctx(c);
+    if (st != NAO_OK) return st;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    std::vector<std::string> keys;
+    std::vector<int64_t> cnt;
+    std::vector<double> ms;
+    for (auto& r : c->recs) {
+        float t = 0.0f;
+        HIP_TRY(c, hipEventElapsedTime(&t, r.a, r.b));
+        size_t k = 0;
+        while (k < keys.size() && keys[k] != r.name) ++k;
+        if (k == keys.size()) {
+            keys.push_back(r.name);
+            cnt.push_back(0);
+            ms.push_back(0.0);
+        }
+        cnt[k]++;
+        ms[k] += t;
+    }
+    const int32_t n = (int32_t)std::min<size_t>(keys.size(), max_entries > 0 ? (size_t)max_entries : 0);
+    for (int32_t k = 0; k < n; ++k) {
+        if (names) {
+            std::memset(names + 32 * k, 0, 32);
+            std::strncpy(names + 32 * k, keys[k].c_str(), 31);
+        }
+        if (launches) launches[k] = cnt[k];
+        if (total_ms) total_ms[k] = ms[k];
+    }
+    if (n_entries) *n_entries = (int32_t)keys.size();
+    return NAO_OK;
+}
+
+// ---------------------------------------------------------------------------------- plans
+
+struct nao_plan_s {
+    HostBasis basis;
+    int64_t n_points = 0;
+    std::vector<int64_t> perm, batch_ptr, atom_ptr;
+    std::vector<int32_t> atoms;
+    std::vector<int64_t> basis_ptr;
+    std::vector<int32_t> basis_idx;
+};
+
+static nao_status check_points(const double* xyz, int64_t n, int32_t max_batch, std::string& why)
+{
+    if (n < 0 || n > 0x7fffffffLL) return (why = "n_points outside [0, 2^31-1]", NAO_ERR_INVALID_ARG);
+    if (n > 0 && !xyz) return (why = "point_xyz is NULL", NAO_ERR_INVALID_ARG);
+    if (max_batch < 1 || max_batch > 4096) return (why = "max_batch outside [1, 4096]", NAO_ERR_INVALID_ARG);
+    if (!finite_all(xyz, 3 * n)) return (why = "non-finite point coordinate", NAO_ERR_INVALID_ARG);
+    return NAO_OK;
+}
+
+nao_status nao_plan_create(const nao_basis_desc* basis, int64_t n_points, const double* point_xyz,
+                           int32_t max_batch, nao_plan* out)
+{
+    if (!out) return (g_thread_error = "out is NULL", NAO_ERR_INVALID_ARG);
+    *out = nullptr;
+    std::string why;
+    nao_status st = check_points(point_xyz, n_points, max_batch, why);
+    if (st != NAO_OK) return (g_thread_error = why, st);
+    try {
+        nao_plan p = new nao_plan_s();
+        why = load_basis(basis, p->basis);
+        if (!why.empty()) {
+            delete p;
+            g_thread_error = why;
+            return NAO_ERR_INVALID_ARG;
+        }
+        p->n_points = n_points;
+        octree_batches(point_xyz, n_points, max_batch, p->perm, p->batch_ptr);
+        relevant_atoms(p->basis, point_xyz, p->perm, p->batch_ptr, p->atom_ptr, p->atoms);
+        expand_lists(p->basis, p->atom_ptr, p->atoms, p->basis_ptr, p->basis_idx);
+        *out = p;
+        return NAO_OK;
+    } catch (const std::bad_alloc&) {
+        g_thread_error = "host allocation failed";
+        return NAO_ERR_OUT_OF_MEMORY;
+    } catch (...) {
+        g_thread_error = "internal error in planning";
+        return NAO_ERR_INTERNAL;
+    }
+}
+
+nao_status nao_plan_info(nao_plan p, int64_t* n_basis, int64_t* n_batches, int64_t* n_list)
+{
+    if (!p) return (g_thread_error = "plan is NULL", NAO_ERR_INVALID_ARG);
+    if (n_basis) *n_basis = p->basis.n_basis;
+    if (n_batches) *n_batches = (int64_t)p->batch_ptr.size() - 1;
+    if (n_list) *n_list = (int64_t)p->basis_idx.size();
+    return NAO_OK;
+}
+
+nao_status nao_plan_get_batches(nao_plan p, int64_t* perm, int64_t* batch_ptr, int64_t* basis_ptr,
+                                int32_t* basis_idx)
+{
+    if (!p) return (g_thread_error = "plan is NULL", NAO_ERR_INVALID_ARG);
+    if (perm) std::copy(p->perm.begin(), p->perm.end(), perm);
+    if (batch_ptr) std::copy(p->batch_ptr.begin(), p->batch_ptr.end(), batch_ptr);
+    if (basis_ptr) std::copy(p->basis_ptr.begin(), p->basis_ptr.end(), basis_ptr);
+    if (basis_idx) std::copy(p->basis_idx.begin(), p->basis_idx.end(), basis_idx);
+    return NAO_OK;
+}
+
+void nao_plan_destroy(nao_plan p) { delete p; }
+
+// -------------------------------------------------------------------------------- systems
+
+static nao_status setup_system(nao_system s, const double* xyz, const double* w)
+{
+    nao_ctx c = s->ctx;
+    const HostBasis& B = s->basis;
+    const int64_t n = s->n_points;
+    octree_batches(xyz, n, s->max_batch, s->perm, s->batch_ptr);
+    relevant_atoms(B, xyz, s->perm, s->batch_ptr, s->atom_ptr, s->atoms);
+    s->work_units = 0.0;
+    for (size_t b = 0; b + 1 < s->batch_ptr.size(); ++b) {
+        double m = 0.0;
+        for (int64_t q = s->atom_ptr[b]; q < s->atom_ptr[b + 1]; ++q)
+            m += (double)(B.atom_first[s->atoms[q] + 1] - B.atom_first[s->atoms[q]]);
+        s->work_units += (double)(s->batch_ptr[b + 1] - s->batch_ptr[b]) * m * m;
+    }
+    // batch-ordered points
+    std::vector<double> px(n), py(n), pz(n), pw(n);
+    std::vector<int32_t> perm32(n);
+    for (int64_t k = 0; k < n; ++k) {
+        const int64_t p = s->perm[k];
+        px[k] = xyz[3 * p];
+        py[k] = xyz[3 * p + 1];
+        pz[k] = xyz[3 * p + 2];
+        pw[k] = w[p];
+        perm32[k] = (int32_t)p;
+    }
+    std::vector<double> axyzr(4 * B.n_atoms);
+    for (int64_t a = 0; a < B.n_atoms; ++a) {
+        axyzr[4 * a] = B.atom_xyz[3 * a];
+        axyzr[4 * a + 1] = B.atom_xyz[3 * a + 1];
+        axyzr[4 * a + 2] = B.atom_xyz[3 * a + 2];
+        axyzr[4 * a + 3] = B.atom_rcut[a] * B.atom_rcut[a];
+    }
+    std::vector<double> rpar(4 * B.n_radial);
+    for (int32_t r = 0; r < B.n_radial; ++r) {
+        rpar[4 * r] = B.rmin[r];
+        rpar[4 * r + 1] = B.rcut[r] * B.rcut[r];
+        rpar[4 * r + 2] = (double)(B.n_knots - 1) / std::log(B.rcut[r] / B.rmin[r]);
+        rpar[4 * r + 3] = std::log(B.rmin[r]);
+    }
+    std::vector<double> spl = spline_coefficients(B);
+    s->spline_lds = spl.size() <= (size_t)MAX_SPLINE_LDS;
+    nao_status st;
+#define UP(arr, vec) \
+    if ((st = upload(c, s->arr, (vec).data(), (vec).size() * sizeof((vec)[0]))) != NAO_OK) return st
+    UP(d_px, px);
+    UP(d_py, py);
+    UP(d_pz, pz);
+    UP(d_pw, pw);
+    UP(d_perm, perm32);
+    UP(d_atoms, axyzr);
+    UP(d_species, B.atom_species);
+    UP(d_shell_ptr, B.shell_ptr);
+    UP(d_shell_l, B.shell_l);
+    UP(d_shell_rad, B.shell_radial);
+    UP(d_radial_par, rpar);
+    UP(d_spline, spl);
+#undef UP
+    DevSys& d = s->dsys;
+    d.px = s->d_px.as<double>();
+    d.py = s->d_py.as<double>();
+    d.pz = s->d_pz.as<double>();
+    d.pw = s->d_pw.as<double>();
+    d.perm = s->d_perm.as<int32_t>();
+    d.atom_xyzr = s->d_atoms.as<double>();
+    d.atom_species = s->d_species.as<int32_t>();
+    d.species_shell_ptr = s->d_shell_ptr.as<int32_t>();
+    d.shell_l = s->d_shell_l.as<int32_t>();
+    d.shell_radial = s->d_shell_rad.as<int32_t>();
+    d.radial_par = s->d_radial_par.as<double>();
+    d.spline = s->d_spline.as<double>();
+    d.n_radial = B.n_radial;
+    d.n_knots = B.n_knots;
+    d.n_basis = B.n_basis;
+    d.n_points = n;
+    if ((st = upload(c, s->d_sys, &d, sizeof(DevSys))) != NAO_OK) return st;
+    if ((st = ensure(c, s->d_wv, std::max<int64_t>(1, n) * sizeof(double))) != NAO_OK) return st;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));  // host vectors above go out of scope
+    return build_groups(s);
+}
+
+nao_status nao_build_batches(nao_ctx c, const nao_basis_desc* basis, int64_t n_points, const double* point_xyz,
+                             const double* point_w, int32_t max_batch, nao_system* out)
+{
+    if (!out) return (set_err(c, "out is NULL"), NAO_ERR_INVALID_ARG);
+    *out = nullptr;
+    nao_status st = check_ctx(c);
+    if (st != NAO_OK) return st;
+    std::string why;
+    if ((st = check_points(point_xyz, n_points, max_batch, why)) != NAO_OK) return (set_err(c, why), st);
+    if (n_points > 0 && !point_w) return (set_err(c, "point_w is NULL"), NAO_ERR_INVALID_ARG);
+    for (int64_t k = 0; k < n_points; ++k)
+        if (!std::isfinite(point_w[k]) || point_w[k] < 0.0)
+            return (set_err(c, "point weights must be finite and >= 0"), NAO_ERR_INVALID_ARG);
+    nao_system s = nullptr;
+    try {
+        s = new nao_system_s();
+        s->ctx = c;
+        why = load_basis(basis, s->basis);
+        if (!why.empty()) {
+            delete s;
+            set_err(c, why);
+            return NAO_ERR_INVALID_ARG;
+        }
+        s->n_points = n_points;
+        s->max_batch = max_batch;
+        st = setup_system(s, point_xyz, point_w);
+    } catch (const std::bad_alloc&) {
+        set_err(c, "host allocation failed");
+        st = NAO_ERR_OUT_OF_MEMORY;
+    } catch (...) {
+        set_err(c, "internal error in nao_build_batches");
+        st = NAO_ERR_INTERNAL;
+    }
+    if (st != NAO_OK) {
+        if (s) {
+            free_all(s);
+            delete s;
+        }
+        return st;
+    }
+    c->n_systems++;
+    *out = s;
+    return NAO_OK;
+}
+
+nao_status nao_system_set_group_max(nao_system s, int32_t group_max)
+{
+    if (!s) return (g_thread_error = "system is NULL", NAO_ERR_INVALID_ARG);
+    nao_status st = check_ctx(s->ctx);
+    if (st != NAO_OK) return st;
+    if (group_max < 16 || group_max > MAX_UNIT_POINTS)
+        return (set_err(s->ctx, "group_max outside [16, 256]"), NAO_ERR_INVALID_ARG);
+    HIP_TRY(s->ctx, hipStreamSynchronize(s->ctx->stream));
+    s->group_max = group_max;
+    try {
+        return build_groups(s);
+    } catch (...) {
+        set_err(s->ctx, "internal error in nao_system_set_group_max");
+        return NAO_ERR_INTERNAL;
+    }
+}
+
+nao_status nao_system_info(nao_system s, int64_t* n_basis, int64_t* n_batches, int64_t* n_list, size_t* dev_bytes)
+{
+    if (!s) return (g_thread_error = "system is NULL", NAO_ERR_INVALID_ARG);
+    if (n_basis) *n_basis = s->basis.n_basis;
+    if (n_batches) *n_batches = (int64_t)s->batch_ptr.size() - 1;
+    if (n_list) {
+        int64_t t = 0;
+        for (size_t b = 0; b + 1 < s->atom_ptr.size(); ++b)
+            for (int64_t q = s->atom_ptr[b]; q < s->atom_ptr[b + 1]; ++q)
+                t += s->basis.atom_first[s->atoms[q] + 1] - s->basis.atom_first[s->atoms[q]];
+        *n_list = t;
+    }
+    if (dev_bytes) *dev_bytes = system_bytes(s);
+    return NAO_OK;
+}
+
+nao_status nao_get_batches(nao_system s, int64_t* perm, int64_t* batch_ptr, int64_t* basis_ptr, int32_t* basis_idx)
+{
+    if (!s) return (g_thread_error = "system is NULL", NAO_ERR_INVALID_ARG);
+    try {
+        if (perm) std::copy(s->perm.begin(), s->perm.end(), perm);
+        if (batch_ptr) std::copy(s->batch_ptr.begin(), s->batch_ptr.end(), batch_ptr);
+        if (basis_ptr || basis_idx) {
+            std::vector<int64_t> bp;
+            std::vector<int32_t> bi;
+            expand_lists(s->basis, s->atom_ptr, s->atoms, bp, bi);
+            if (basis_ptr) std::copy(bp.begin(), bp.end(), basis_ptr);
+            if (basis_idx) std::copy(bi.begin(), bi.end(), basis_idx);
+        }
+    } catch (...) {
+        set_err(s->ctx, "host allocation failed");
+        return NAO_ERR_OUT_OF_MEMORY;
+    }
+    return NAO_OK;
+}
+
+nao_status nao_system_work(nao_system s, double* units)
+{
+    if (!s || !units) return (g_thread_error = "NULL argument", NAO_ERR_INVALID_ARG);
+    *units = s->work_units;
+    return NAO_OK;
+}
+
+void nao_system_destroy(nao_system s)
+{
+    if (!s) return;
+    (void)hipSetDevice(s->ctx->device);
+    (void)hipStreamSynchronize(s->ctx->stream);
+    free_all(s);
+    s->ctx->n_systems--;
+    delete s;
+}
+
+// ------------------------------------------------------------------------------ basis values
+
+nao_status nao_eval_basis(nao_system s, int64_t b0, int64_t b1, double* phi, nao_memspace phi_space,
+                          int64_t* phi_ptr)
+{
+    if (!s) return (g_thread_error = "system is NULL", NAO_ERR_INVALID_ARG);
+    nao_ctx c = s->ctx;
+    nao_status st = check_ctx(c);
+    if (st != NAO_OK) return st;
+    const int64_t nb = (int64_t)s->batch_ptr.size() - 1;
+    if (b0 < 0 || b1 < b0 || b1 > nb) return (set_err(c, "batch range out of bounds"), NAO_ERR_INVALID_ARG);
+    if (!phi_ptr) return (set_err(c, "phi_ptr is NULL"), NAO_ERR_INVALID_ARG);
+    if (phi_space != NAO_MEM_HOST && phi_space != NAO_MEM_DEVICE) return (set_err(c, "bad memspace"), NAO_ERR_INVALID_ARG);
+    std::vector<Unit> units;
+    std::vector<int32_t> uat, ucol;
+    try {
+        batch_units(s->basis, s->batch_ptr, s->atom_ptr, s->atoms, b0, b1, units, uat, ucol);
+    } catch (...) {
+        return (set_err(c, "host allocation failed"), NAO_ERR_OUT_OF_MEMORY);
+    }
+    phi_ptr[0] = 0;
+    std::vector<DevUnit> du;
+    for (size_t k = 0; k < units.size(); ++k) {
+        const Unit& u = units[k];
+        phi_ptr[k + 1] = phi_ptr[k] + (int64_t)u.n_points * u.m;
+        if (u.m == 0 || u.n_points == 0) continue;
+        DevUnit d{};
+        d.point_begin = u.point_begin;
+        d.atom_begin = u.atom_begin;
+        d.fn_begin = 0;
+        d.out_offset = phi_ptr[k];
+        d.n_points = u.n_points;
+        d.n_atoms = u.n_atoms;
+        d.m = u.m;
+        d.ld = u.m;
+        du.push_back(d);
+    }
+    if (!phi || du.empty()) return NAO_OK;
+    const int64_t total = phi_ptr[units.size()];
+    DevArray t_units, t_at, t_col, t_out, t_seg;
+    auto cleanup = [&]() {
+        (void)hipStreamSynchronize(c->stream);
+        for (DevArray* a : {&t_units, &t_at, &t_col, &t_out, &t_seg}) dev_free(c, a->p, a->bytes);
+    };
+    if ((st = upload(c, t_units, du.data(), du.size() * sizeof(DevUnit))) != NAO_OK) return cleanup(), st;
+    if ((st = upload(c, t_at, uat.data(), uat.size() * sizeof(int32_t))) != NAO_OK) return cleanup(), st;
+    if ((st = upload(c, t_col, ucol.data(), ucol.size() * sizeof(int32_t))) != NAO_OK) return cleanup(), st;
+    double* out = phi;
+    if (phi_space == NAO_MEM_HOST) {
+        if ((st = ensure(c, t_out, (size_t)total * sizeof(double))) != NAO_OK) return cleanup(), st;
+        out = t_out.as<double>();
+    }
+    DevSeg g{};
+    g.sys = s->d_sys.as<DevSys>();
+    g.units = t_units.as<DevUnit>();
+    g.unit_atoms = t_at.as<int32_t>();
+    g.unit_cols = t_col.as<int32_t>();
+    g.phi = out;
+    g.unit_begin = 0;
+    g.unit_count = (int64_t)du.size();
+    g.unit_prefix = 0;
+    if ((st = upload(c, t_seg, &g, sizeof(DevSeg))) != NAO_OK) return cleanup(), st;
+    hipError_t e = launch_basis_f64(t_seg.as<DevSeg>(), 1, (int64_t)du.size(), s->spline_lds, c->stream);
+    if (e == hipSuccess && phi_space == NAO_MEM_HOST)
+        e = hipMemcpyAsync(phi, out, (size_t)total * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    cleanup();
+    if (e != hipSuccess) return hip_fail(c, e, "nao_eval_basis");
+    return NAO_OK;
+}
+
+// ------------------------------------------------------------------------------ contractions
+
+static nao_status check_prec(nao_ctx c, nao_precision p)
+{
+    if (p == NAO_FP64) return NAO_OK;
+    if (p == NAO_FP32 || p == NAO_BF16X3 || p == NAO_BF16X6)
+        return (set_err(c, "this precision is not available in this build"), NAO_ERR_INVALID_ARG);
+    return (set_err(c, "unknown precision"), NAO_ERR_INVALID_ARG);
+}
+
+static nao_status run_blocks(nao_system s, bool ham, const double* wv, const double* D, double* H, double* n)
+{
+    nao_ctx c = s->ctx;
+    std::vector<DevSeg> segs;
+    for (const Block& b : s->blocks) {
+        DevSeg g = make_seg(s, b, ham);
+        g.wv = wv;
+        g.D = D;
+        g.H = H;
+        g.n = n;
+        segs.push_back(g);
+    }
+    if (segs.empty()) return NAO_OK;
+    HIP_TRY(c, hipMemcpyAsync(s->d_segs.p, segs.data(), segs.size() * sizeof(DevSeg), hipMemcpyHostToDevice,
+                              c->stream));
+    DevSeg* dseg = s->d_segs.as<DevSeg>();
+    for (size_t k = 0; k < segs.size(); ++k) {
+        LAUNCH(c, "basis_f64", launch_basis_f64(dseg + k, 1, segs[k].unit_count, s->spline_lds, c->stream));
+        if (ham)
+            LAUNCH(c, "h_f64", launch_h_f64(dseg + k, 1, segs[k].item_count, c->stream));
+        else
+            LAUNCH(c, "n_f64", launch_n_f64(dseg + k, 1, segs[k].item_count, c->stream));
+    }
+    return NAO_OK;
+}
+
+nao_status nao_integrate_h(nao_system s, const double* v, nao_memspace v_space, nao_precision prec, double* H,
+                           nao_memspace H_space)
+{
+    if (!s) return (g_thread_error = "system is NULL", NAO_ERR_INVALID_ARG);
+    nao_ctx c = s->ctx;
+    nao_status st = check_ctx(c);
+    if (st != NAO_OK) return st;
+    if ((st = check_prec(c, prec)) != NAO_OK) return st;
+    if (!H || (s->n_points > 0 && !v)) return (set_err(c, "NULL v or H"), NAO_ERR_INVALID_ARG);
+    if ((v_space != NAO_MEM_HOST && v_space != NAO_MEM_DEVICE) || (H_space != NAO_MEM_HOST && H_space != NAO_MEM_DEVICE))
+        return (set_err(c, "bad memspace"), NAO_ERR_INVALID_ARG);
+    const int64_t n = s->n_points, nb = s->basis.n_basis;
+    const double* vd = v;
+    if (v_space == NAO_MEM_HOST && n > 0) {
+        if ((st = ensure(c, s->d_v, n * sizeof(double))) != NAO_OK) return st;
+        HIP_TRY(c, hipMemcpyAsync(s->d_v.p, v, n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+        vd = s->d_v.as<double>();
+    }
+    double* Hd = H;
+    if (H_space == NAO_MEM_HOST) {
+        if ((st = ensure(c, s->d_H, std::max<int64_t>(1, nb * nb) * sizeof(double))) != NAO_OK) return st;
+        Hd = s->d_H.as<double>();
+    }
+    LAUNCH(c, "fill", launch_fill(Hd, nb * nb, 0.0, c->stream));
+    LAUNCH(c, "wv", launch_wv(s->d_pw.as<double>(), s->d_perm.as<int32_t>(), vd, s->d_wv.as<double>(), n, c->stream));
+    if ((st = run_blocks(s, true, s->d_wv.as<double>(), nullptr, Hd, nullptr)) != NAO_OK) return st;
+    LAUNCH(c, "mirror", launch_mirror(Hd, nb, c->stream));
+    if (H_space == NAO_MEM_HOST) {
+        HIP_TRY(c, hipMemcpyAsync(H, Hd, nb * nb * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+    }
+    if (v_space == NAO_MEM_HOST) HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return NAO_OK;
+}
+
+nao_status nao_update_density(nao_system s, const double* D, nao_memspace D_space, nao_precision prec, double* nout,
+                              nao_memspace n_space, double* n_electrons)
+{
+    if (!s) return (g_thread_error = "system is NULL", NAO_ERR_INVALID_ARG);
+    nao_ctx c = s->ctx;
+    nao_status st = check_ctx(c);
+    if (st != NAO_OK) return st;
+    if ((st = check_prec(c, prec)) != NAO_OK) return st;
+    const int64_t n = s->n_points, nb = s->basis.n_basis;
+    if ((nb > 0 && !D) || (n > 0 && !nout)) return (set_err(c, "NULL D or n"), NAO_ERR_INVALID_ARG);
+    if ((D_space != NAO_MEM_HOST && D_space != NAO_MEM_DEVICE) || (n_space != NAO_MEM_HOST && n_space != NAO_MEM_DEVICE))
+        return (set_err(c, "bad memspace"), NAO_ERR_INVALID_ARG);
+    const double* Dd = D;
+    if (D_space == NAO_MEM_HOST && nb > 0) {
+        if ((st = ensure(c, s->d_D, nb * nb * sizeof(double))) != NAO_OK) return st;
+        HIP_TRY(c, hipMemcpyAsync(s->d_D.p, D, nb * nb * sizeof(double), hipMemcpyHostToDevice, c->stream));
+        Dd = s->d_D.as<double>();
+    }
+    double* nd = nout;
+    if (n_space == NAO_MEM_HOST) {
+        if ((st = ensure(c, s->d_n, std::max<int64_t>(1, n) * sizeof(double))) != NAO_OK) return st;
+        nd = s->d_n.as<double>();
+    }
+    LAUNCH(c, "fill", launch_fill(nd, n, 0.0, c->stream));
+    if ((st = run_blocks(s, false, nullptr, Dd, nullptr, nd)) != NAO_OK) return st;
+    if (n_electrons) {
+        LAUNCH(c, "electron_count", launch_weighted_sum(s->d_pw.as<double>(), s->d_perm.as<int32_t>(), nd, n,
+                                                         c->wsum, c->wsum + WSUM_BLOCKS, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(n_electrons, c->wsum + WSUM_BLOCKS, sizeof(double), hipMemcpyDeviceToHost,
+                                  c->stream));
+    }
+    if (n_space == NAO_MEM_HOST && n > 0)
+        HIP_TRY(c, hipMemcpyAsync(nout, nd, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    if (n_space == NAO_MEM_HOST || n_electrons || D_space == NAO_MEM_HOST) HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return NAO_OK;
+}
+
+nao_status nao_run_many(nao_ctx c, const nao_work* work, int64_t n_work, nao_precision prec, uint32_t flags)
+{
+    (void)work;
+    (void)n_work;
+    (void)prec;
+    (void)flags;
+    set_err(c, "nao_run_many is not available in this build");
+    return NAO_ERR_NOT_READY;
+}
+
+}  // extern "C"
