@@ -220,6 +220,51 @@ typedef struct {
 
 nao_status nao_run_many(nao_ctx ctx, const nao_work* work, int64_t n_work, nao_precision precision,
                         uint32_t flags);
+/* Without NAO_RUN_CAPTURE_GRAPH, systems may also belong to another context on the same device
+ * (the work then runs on ctx's stream with ctx's scratch); such a system must not be destroyed
+ * while that work runs. */
+
+/* ---------------------------------------------------------------------------------------
+ * Serving core: continuous batching of SCF-iteration requests over resident structures.
+ *
+ * A server owns n_slots execution slots on the device of `home` (each a context with its own
+ * HIP stream of default priority and its own scratch).  A session is one structure kept
+ * resident in device memory across its SCF iterations (its system plus device buffers for D,
+ * v, H and n), allocated through `home`, whose HBM budget therefore bounds what is resident:
+ * sessions are admitted in the order they were opened, when their footprint fits
+ * (NAO_ERR_BUDGET from the allocation means "wait").  A request is one iteration: a density
+ * update from the given D, then the Hamiltonian with the given v (the last v is kept when v
+ * is NULL).  nao_server_step never blocks: it retires finished launches, admits waiting
+ * sessions, and packs the oldest ready requests (at most one per session in flight, up to
+ * max_per_launch per launch) into each free slot as one nao_run_many launch, so requests that
+ * arrive while others run join the next launch on a free slot and overlap on the device.
+ * Inputs D and v stay owned by the caller and must stay valid until the request is done.
+ * Times are seconds since the server was created (host steady clock).
+ * ------------------------------------------------------------------------------------- */
+typedef struct nao_server_s* nao_server;
+
+typedef enum { NAO_REQ_WAITING = 0, NAO_REQ_RUNNING = 1, NAO_REQ_DONE = 2 } nao_request_state;
+
+nao_status nao_server_create(nao_ctx home, int32_t n_slots, int32_t max_per_launch, nao_precision precision,
+                             nao_server* out);
+/* Queue a structure (copied); returns its session id.  Admission happens in nao_server_step. */
+nao_status nao_server_open_session(nao_server srv, const nao_basis_desc* basis, int64_t n_points,
+                                   const double* point_xyz, const double* point_w, int32_t max_batch,
+                                   int64_t* session);
+/* The session's resources are released once its last request is done. */
+nao_status nao_server_close_session(nao_server srv, int64_t session);
+/* resident: 1 once admitted; bytes: its device footprint (0 before admission). */
+nao_status nao_server_session_info(nao_server srv, int64_t session, int32_t* resident, size_t* bytes,
+                                   int64_t* n_basis, int64_t* n_points);
+nao_status nao_server_submit(nao_server srv, int64_t session, const double* D, nao_memspace D_space,
+                             const double* v, nao_memspace v_space, uint64_t* ticket);
+nao_status nao_server_step(nao_server srv, int32_t* n_running, int32_t* n_waiting);
+nao_status nao_server_poll(nao_server srv, uint64_t ticket, int32_t* state, double* t_submit, double* t_start,
+                           double* t_end);
+/* Copy a done request's H [N_b][N_b] and/or n [n_points] (caller order) out; either may be NULL.
+ * Valid until the session's next request starts. */
+nao_status nao_server_result(nao_server srv, uint64_t ticket, double* H, double* n, nao_memspace space);
+void nao_server_destroy(nao_server srv);
 
 #ifdef __cplusplus
 }

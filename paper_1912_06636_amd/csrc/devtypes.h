@@ -67,7 +67,8 @@ struct DevSeg {
     const int32_t* unit_cols;
     const int32_t* unit_fn;
     const void* items;       // HItem* or NItem*
-    double* phi;             // basis values of this block (unit.out_offset is relative to it)
+    void* phi;               // basis values of this block (FP64, or FP32 for the reduced-precision
+                             // modes); unit.out_offset is relative to it
     const double* wv;        // batch-ordered w*v (Hamiltonian)
     const double* D;         // density matrix (density), row-major, ld = n_basis
     double* H;               // Hamiltonian, row-major, ld = n_basis
@@ -81,10 +82,17 @@ struct DevSeg {
 // kernel launchers (kernels.hip).  Every launcher checks its own grid against the segment
 // table before launching and returns hipErrorInvalidValue on a mismatch.
 
-hipError_t launch_basis_f64(const DevSeg* segs_dev, int n_segs, int64_t n_units, bool spline_in_lds,
-                            hipStream_t st);
-hipError_t launch_h_f64(const DevSeg* segs_dev, int n_segs, int64_t n_items, hipStream_t st);
-hipError_t launch_n_f64(const DevSeg* segs_dev, int n_segs, int64_t n_items, hipStream_t st);
+// Contraction arithmetic (nao_precision values).
+enum Mode { MODE_FP64 = 0, MODE_FP32 = 1, MODE_BF16X3 = 2, MODE_BF16X6 = 3 };
+
+// Basis values as FP64 (fp32_out = false) or rounded to FP32.
+// max_grid > 0 caps the grid: workgroups then loop over the items (persistent launch).
+hipError_t launch_basis(const DevSeg* segs_dev, int n_segs, int64_t n_units, bool spline_in_lds, bool fp32_out,
+                        hipStream_t st, int64_t max_grid = 0);
+hipError_t launch_h(Mode mode, const DevSeg* segs_dev, int n_segs, int64_t n_items, hipStream_t st,
+                    int64_t max_grid = 0);
+hipError_t launch_n(Mode mode, const DevSeg* segs_dev, int n_segs, int64_t n_items, hipStream_t st,
+                    int64_t max_grid = 0);
 hipError_t launch_fill(double* p, int64_t n, double value, hipStream_t st);
 hipError_t launch_wv(const double* pw, const int32_t* perm, const double* v_caller, double* wv,
                      int64_t n_points, hipStream_t st);

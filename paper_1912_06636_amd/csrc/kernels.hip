@@ -39,10 +39,6 @@ __device__ inline double dist2_exact(double dx, double dy, double dz)
 }
 
 // Real orthonormal spherical harmonics (l <= 3) of a unit vector, m = -l..l; Y_11 ~ +x.
-struct Ylm {
-    double v[16];
-};
-
 __device__ inline void real_ylm(double x, double y, double z, int lmax, double* Y)
 {
     const double c00 = 0.28209479177387814;   // 1 / (2 sqrt(pi))
@@ -82,118 +78,128 @@ __device__ inline void real_ylm(double x, double y, double z, int lmax, double* 
 // ------------------------------------------------------------------------------------------
 // basis evaluation: one workgroup per unit, threads over (point, atom) pairs (atom fastest)
 
-template <bool SPLINE_LDS>
-__global__ __launch_bounds__(256) void basis_kernel_f64(const DevSeg* __restrict__ segs, int n_segs)
+template <typename T, bool SPLINE_LDS>
+__global__ __launch_bounds__(256) void basis_kernel(const DevSeg* __restrict__ segs, int n_segs, int64_t total)
 {
     extern __shared__ double lds_spline[];
-    const int64_t b = blockIdx.x;
-    const int s = find_segment(segs, n_segs, b, [](const DevSeg& g) { return g.unit_prefix; });
-    const DevSeg& sg = segs[s];
-    const DevUnit u = sg.units[sg.unit_begin + (b - sg.unit_prefix)];
-    const DevSys* S = sg.sys;
-    const int nk = S->n_knots;
-    const double* spl = S->spline;
-    if (SPLINE_LDS) {
-        const int nsp = S->n_radial * (nk - 1) * 4;
-        for (int i = threadIdx.x; i < nsp; i += blockDim.x) lds_spline[i] = spl[i];
-        __syncthreads();
-    }
-    double* __restrict__ out = sg.phi + u.out_offset;
-    const int64_t npairs = (int64_t)u.n_points * u.n_atoms;
-    const double tmax = (double)(nk - 1);
-    for (int64_t q = threadIdx.x; q < npairs; q += blockDim.x) {
-        const int pl = (int)(q / u.n_atoms);
-        const int ai = (int)(q - (int64_t)pl * u.n_atoms);
-        const int atom = sg.unit_atoms[u.atom_begin + ai];
-        int col = sg.unit_cols[u.atom_begin + ai];
-        const int64_t p = u.point_begin + pl;
-        const double* A = S->atom_xyzr + 4 * (int64_t)atom;
-        const double dx = S->px[p] - A[0];
-        const double dy = S->py[p] - A[1];
-        const double dz = S->pz[p] - A[2];
-        const double d2 = dist2_exact(dx, dy, dz);
-        const int sp = S->atom_species[atom];
-        const int sh0 = S->species_shell_ptr[sp], sh1 = S->species_shell_ptr[sp + 1];
-        double* row = out + (int64_t)pl * u.ld;
-        if (d2 >= A[3]) {
+    for (int64_t b = blockIdx.x; b < total; b += gridDim.x) {
+        __syncthreads();  // the previous item may still read LDS
+        const int s = find_segment(segs, n_segs, b, [](const DevSeg& g) { return g.unit_prefix; });
+        const DevSeg& sg = segs[s];
+        const DevUnit u = sg.units[sg.unit_begin + (b - sg.unit_prefix)];
+        const DevSys* S = sg.sys;
+        const int nk = S->n_knots;
+        const double* spl = S->spline;
+        if (SPLINE_LDS) {
+            const int nsp = S->n_radial * (nk - 1) * 4;
+            for (int i = threadIdx.x; i < nsp; i += blockDim.x) lds_spline[i] = spl[i];
+            __syncthreads();
+        }
+        T* __restrict__ out = static_cast<T*>(sg.phi) + u.out_offset;
+        const int64_t npairs = (int64_t)u.n_points * u.n_atoms;
+        const double tmax = (double)(nk - 1);
+        for (int64_t q = threadIdx.x; q < npairs; q += blockDim.x) {
+            const int pl = (int)(q / u.n_atoms);
+            const int ai = (int)(q - (int64_t)pl * u.n_atoms);
+            const int atom = sg.unit_atoms[u.atom_begin + ai];
+            int col = sg.unit_cols[u.atom_begin + ai];
+            const int64_t p = u.point_begin + pl;
+            const double* A = S->atom_xyzr + 4 * (int64_t)atom;
+            const double dx = S->px[p] - A[0];
+            const double dy = S->py[p] - A[1];
+            const double dz = S->pz[p] - A[2];
+            const double d2 = dist2_exact(dx, dy, dz);
+            const int sp = S->atom_species[atom];
+            const int sh0 = S->species_shell_ptr[sp], sh1 = S->species_shell_ptr[sp + 1];
+            T* row = out + (int64_t)pl * u.ld;
+            if (d2 >= A[3]) {
+                for (int j = sh0; j < sh1; ++j) {
+                    const int nf = 2 * S->shell_l[j] + 1;
+                    for (int f = 0; f < nf; ++f) row[col + f] = T(0);
+                    col += nf;
+                }
+                continue;
+            }
+            const double r = sqrt(d2);
+            double ux = 0.0, uy = 0.0, uz = 1.0;
+            if (r > 0.0) {
+                const double ir = 1.0 / r;
+                ux = dx * ir;
+                uy = dy * ir;
+                uz = dz * ir;
+            }
+            int lmax = 0;
+            for (int j = sh0; j < sh1; ++j) lmax = max(lmax, S->shell_l[j]);
+            double Y[16];
+            real_ylm(ux, uy, uz, lmax, Y);
+            const double lnr = r > 0.0 ? log(r) : 0.0;
             for (int j = sh0; j < sh1; ++j) {
-                const int nf = 2 * S->shell_l[j] + 1;
-                for (int f = 0; f < nf; ++f) row[col + f] = 0.0;
-                col += nf;
-            }
-            continue;
-        }
-        const double r = sqrt(d2);
-        double ux = 0.0, uy = 0.0, uz = 1.0;
-        if (r > 0.0) {
-            const double ir = 1.0 / r;
-            ux = dx * ir;
-            uy = dy * ir;
-            uz = dz * ir;
-        }
-        int lmax = 0;
-        for (int j = sh0; j < sh1; ++j) lmax = max(lmax, S->shell_l[j]);
-        double Y[16];
-        real_ylm(ux, uy, uz, lmax, Y);
-        const double lnr = r > 0.0 ? log(r) : 0.0;
-        for (int j = sh0; j < sh1; ++j) {
-            const int l = S->shell_l[j];
-            const int rr = S->shell_radial[j];
-            const double* par = S->radial_par + 4 * rr;
-            double R = 0.0;
-            if (d2 < par[1]) {
-                double t = r > par[0] ? (lnr - par[3]) * par[2] : 0.0;
-                t = fmin(fmax(t, 0.0), tmax);
-                const int k = min((int)t, nk - 2);
-                const double w = t - (double)k;
-                const double* c = (SPLINE_LDS ? lds_spline : spl) + ((int64_t)rr * (nk - 1) + k) * 4;
-                R = c[0] + w * (c[1] + w * (c[2] + w * c[3]));
-            }
-            switch (l) {
-            case 0:
-                row[col] = R * Y[0];
-                col += 1;
-                break;
-            case 1:
-                row[col] = R * Y[1];
-                row[col + 1] = R * Y[2];
-                row[col + 2] = R * Y[3];
-                col += 3;
-                break;
-            case 2:
-#pragma unroll
-                for (int f = 0; f < 5; ++f) row[col + f] = R * Y[4 + f];
-                col += 5;
-                break;
-            default:
-#pragma unroll
-                for (int f = 0; f < 7; ++f) row[col + f] = R * Y[9 + f];
-                col += 7;
-                break;
+                const int l = S->shell_l[j];
+                const int rr = S->shell_radial[j];
+                const double* par = S->radial_par + 4 * rr;
+                double R = 0.0;
+                if (d2 < par[1]) {
+                    double t = r > par[0] ? (lnr - par[3]) * par[2] : 0.0;
+                    t = fmin(fmax(t, 0.0), tmax);
+                    const int k = min((int)t, nk - 2);
+                    const double w = t - (double)k;
+                    const double* c = (SPLINE_LDS ? lds_spline : spl) + ((int64_t)rr * (nk - 1) + k) * 4;
+                    R = c[0] + w * (c[1] + w * (c[2] + w * c[3]));
+                }
+                switch (l) {
+                case 0:
+                    row[col] = T(R * Y[0]);
+                    col += 1;
+                    break;
+                case 1:
+                    row[col] = T(R * Y[1]);
+                    row[col + 1] = T(R * Y[2]);
+                    row[col + 2] = T(R * Y[3]);
+                    col += 3;
+                    break;
+                case 2:
+    #pragma unroll
+                    for (int f = 0; f < 5; ++f) row[col + f] = T(R * Y[4 + f]);
+                    col += 5;
+                    break;
+                default:
+    #pragma unroll
+                    for (int f = 0; f < 7; ++f) row[col + f] = T(R * Y[9 + f]);
+                    col += 7;
+                    break;
+                }
             }
         }
-    }
-    const int pad = u.ld - u.m;
-    if (pad > 0) {
-        const int64_t np = (int64_t)u.n_points * pad;
-        for (int64_t q = threadIdx.x; q < np; q += blockDim.x) {
-            const int64_t pl = q / pad;
-            out[pl * u.ld + u.m + (q - pl * pad)] = 0.0;
+        const int pad = u.ld - u.m;
+        if (pad > 0) {
+            const int64_t np = (int64_t)u.n_points * pad;
+            for (int64_t q = threadIdx.x; q < np; q += blockDim.x) {
+                const int64_t pl = q / pad;
+                out[pl * u.ld + u.m + (q - pl * pad)] = T(0);
+            }
         }
     }
 }
 
-hipError_t launch_basis_f64(const DevSeg* segs_dev, int n_segs, int64_t n_units, bool spline_in_lds,
-                            hipStream_t st)
+static unsigned grid_for(int64_t n, int64_t max_grid)
+{
+    return (unsigned)((max_grid > 0 && n > max_grid) ? max_grid : n);
+}
+
+hipError_t launch_basis(const DevSeg* segs_dev, int n_segs, int64_t n_units, bool spline_in_lds, bool fp32_out,
+                        hipStream_t st, int64_t max_grid)
 {
     if (n_units <= 0 || n_segs <= 0) return hipSuccess;
     if (n_units > 0x7fffffff) return hipErrorInvalidValue;
-    if (spline_in_lds)
-        hipLaunchKernelGGL(basis_kernel_f64<true>, dim3((unsigned)n_units), dim3(256),
-                           MAX_SPLINE_LDS * sizeof(double), st, segs_dev, n_segs);
-    else
-        hipLaunchKernelGGL(basis_kernel_f64<false>, dim3((unsigned)n_units), dim3(256), 0, st, segs_dev,
-                           n_segs);
+    const dim3 g(grid_for(n_units, max_grid)), b(256);
+    const size_t lds = spline_in_lds ? MAX_SPLINE_LDS * sizeof(double) : 0;
+    if (fp32_out) {
+        if (spline_in_lds) hipLaunchKernelGGL((basis_kernel<float, true>), g, b, lds, st, segs_dev, n_segs, n_units);
+        else hipLaunchKernelGGL((basis_kernel<float, false>), g, b, 0, st, segs_dev, n_segs, n_units);
+    } else {
+        if (spline_in_lds) hipLaunchKernelGGL((basis_kernel<double, true>), g, b, lds, st, segs_dev, n_segs, n_units);
+        else hipLaunchKernelGGL((basis_kernel<double, false>), g, b, 0, st, segs_dev, n_segs, n_units);
+    }
     return hipGetLastError();
 }
 
@@ -203,86 +209,80 @@ hipError_t launch_basis_f64(const DevSeg* segs_dev, int n_segs, int64_t n_units,
 // K loop over the unit's points in chunks of 16 staged in LDS; four waves, each a 32x32
 // quarter as 2x2 blocks of v_mfma_f64_16x16x4; FP64 atomics into the upper triangle.
 
-__global__ __launch_bounds__(256) void h_kernel_f64(const DevSeg* __restrict__ segs, int n_segs)
+__global__ __launch_bounds__(256) void h_kernel_f64(const DevSeg* __restrict__ segs, int n_segs, int64_t total)
 {
     __shared__ double As[KCHUNK][TILE + 2];
     __shared__ double Bs[KCHUNK][TILE + 2];
-    const int64_t b = blockIdx.x;
-    const int s = find_segment(segs, n_segs, b, [](const DevSeg& g) { return g.item_prefix; });
-    const DevSeg& sg = segs[s];
-    const HItem it = static_cast<const HItem*>(sg.items)[sg.item_begin + (b - sg.item_prefix)];
-    const DevUnit u = sg.units[it.unit];
-    const double* __restrict__ phi = sg.phi + u.out_offset;
-    const double* __restrict__ wv = sg.wv + u.point_begin;
-    const int np = u.n_points, ld = u.ld;
-    const int I0 = it.ti * TILE, J0 = it.tj * TILE;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wr = wave >> 1, wc = wave & 1;
-    const int lr = lane & 15, lk = lane >> 4;
+    for (int64_t b = blockIdx.x; b < total; b += gridDim.x) {
+        const int s = find_segment(segs, n_segs, b, [](const DevSeg& g) { return g.item_prefix; });
+        const DevSeg& sg = segs[s];
+        const HItem it = static_cast<const HItem*>(sg.items)[sg.item_begin + (b - sg.item_prefix)];
+        const DevUnit u = sg.units[it.unit];
+        const double* __restrict__ phi = static_cast<const double*>(sg.phi) + u.out_offset;
+        const double* __restrict__ wv = sg.wv + u.point_begin;
+        const int np = u.n_points, ld = u.ld;
+        const int I0 = it.ti * TILE, J0 = it.tj * TILE;
+        const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+        const int wr = wave >> 1, wc = wave & 1;
+        const int lr = lane & 15, lk = lane >> 4;
 
-    d4 acc[2][2];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+        d4 acc[2][2];
+    #pragma unroll
+        for (int i = 0; i < 2; ++i)
+    #pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
 
-    for (int k0 = 0; k0 < np; k0 += KCHUNK) {
-#pragma unroll
-        for (int e = tid; e < KCHUNK * TILE; e += 256) {
-            const int r = e >> 6, c = e & 63;
-            const int p = k0 + r;
-            double a = 0.0, bb = 0.0;
-            if (p < np) {
-                const double* rowp = phi + (int64_t)p * ld;
-                a = rowp[I0 + c] * wv[p];
-                bb = rowp[J0 + c];
-            }
-            As[r][c] = a;
-            Bs[r][c] = bb;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int kk = 0; kk < KCHUNK / 4; ++kk) {
-            const int kr = kk * 4 + lk;
-            const double a0 = As[kr][wr * 32 + lr];
-            const double a1 = As[kr][wr * 32 + 16 + lr];
-            const double b0 = Bs[kr][wc * 32 + lr];
-            const double b1 = Bs[kr][wc * 32 + 16 + lr];
-            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
-        }
-        __syncthreads();
-    }
-
-    const int32_t* __restrict__ fn = sg.unit_fn + u.fn_begin;
-    double* __restrict__ H = sg.H;
-    const int64_t ldh = sg.ld;
-    const bool diag = it.ti == it.tj;
-#pragma unroll
-    for (int ib = 0; ib < 2; ++ib)
-#pragma unroll
-        for (int jb = 0; jb < 2; ++jb)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = wr * 32 + ib * 16 + lk * 4 + r;
-                const int col = wc * 32 + jb * 16 + lr;
-                const int ci = I0 + row, cj = J0 + col;
-                if (ci < u.m && cj < u.m && (!diag || row <= col)) {
-                    const int64_t gi = fn[ci], gj = fn[cj];
-                    unsafeAtomicAdd(H + gi * ldh + gj, acc[ib][jb][r]);
+        for (int k0 = 0; k0 < np; k0 += KCHUNK) {
+    #pragma unroll
+            for (int e = tid; e < KCHUNK * TILE; e += 256) {
+                const int r = e >> 6, c = e & 63;
+                const int p = k0 + r;
+                double a = 0.0, bb = 0.0;
+                if (p < np) {
+                    const double* rowp = phi + (int64_t)p * ld;
+                    a = rowp[I0 + c] * wv[p];
+                    bb = rowp[J0 + c];
                 }
+                As[r][c] = a;
+                Bs[r][c] = bb;
             }
+            __syncthreads();
+    #pragma unroll
+            for (int kk = 0; kk < KCHUNK / 4; ++kk) {
+                const int kr = kk * 4 + lk;
+                const double a0 = As[kr][wr * 32 + lr];
+                const double a1 = As[kr][wr * 32 + 16 + lr];
+                const double b0 = Bs[kr][wc * 32 + lr];
+                const double b1 = Bs[kr][wc * 32 + 16 + lr];
+                acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+                acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+                acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+                acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+            }
+            __syncthreads();
+        }
+
+        const int32_t* __restrict__ fn = sg.unit_fn + u.fn_begin;
+        double* __restrict__ H = sg.H;
+        const int64_t ldh = sg.ld;
+        const bool diag = it.ti == it.tj;
+    #pragma unroll
+        for (int ib = 0; ib < 2; ++ib)
+    #pragma unroll
+            for (int jb = 0; jb < 2; ++jb)
+    #pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = wr * 32 + ib * 16 + lk * 4 + r;
+                    const int col = wc * 32 + jb * 16 + lr;
+                    const int ci = I0 + row, cj = J0 + col;
+                    if (ci < u.m && cj < u.m && (!diag || row <= col)) {
+                        const int64_t gi = fn[ci], gj = fn[cj];
+                        unsafeAtomicAdd(H + gi * ldh + gj, acc[ib][jb][r]);
+                    }
+                }
+    }
 }
 
-hipError_t launch_h_f64(const DevSeg* segs_dev, int n_segs, int64_t n_items, hipStream_t st)
-{
-    if (n_items <= 0 || n_segs <= 0) return hipSuccess;
-    if (n_items > 0x7fffffff) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(h_kernel_f64, dim3((unsigned)n_items), dim3(256), 0, st, segs_dev, n_segs);
-    return hipGetLastError();
-}
 
 // ------------------------------------------------------------------------------------------
 // Density: per work item one 64-wide column tile J of a unit,
@@ -292,95 +292,505 @@ hipError_t launch_h_f64(const DevSeg* segs_dev, int n_segs, int64_t n_items, hip
 // Rows = the unit's points (<= 256, 16 row blocks), K = basis functions in chunks of 16;
 // wave w owns column block w (16 columns) for all row blocks.
 
-__global__ __launch_bounds__(256) void n_kernel_f64(const DevSeg* __restrict__ segs, int n_segs)
+__global__ __launch_bounds__(256) void n_kernel_f64(const DevSeg* __restrict__ segs, int n_segs, int64_t total)
 {
     __shared__ double As[MAX_UNIT_POINTS][KCHUNK + 1];
     __shared__ double Bs[KCHUNK][TILE + 2];
     __shared__ double red[4][MAX_UNIT_POINTS];
-    const int64_t b = blockIdx.x;
-    const int s = find_segment(segs, n_segs, b, [](const DevSeg& g) { return g.item_prefix; });
-    const DevSeg& sg = segs[s];
-    const NItem it = static_cast<const NItem*>(sg.items)[sg.item_begin + (b - sg.item_prefix)];
-    const DevUnit u = sg.units[it.unit];
-    const double* __restrict__ phi = sg.phi + u.out_offset;
-    const int32_t* __restrict__ fn = sg.unit_fn + u.fn_begin;
-    const double* __restrict__ D = sg.D;
-    const int64_t ldd = sg.ld;
-    const int np = u.n_points, ld = u.ld, m = u.m;
-    const int P = (np + 15) >> 4;
-    const int J0 = it.tj * TILE;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int lr = lane & 15, lk = lane >> 4;
+    for (int64_t b = blockIdx.x; b < total; b += gridDim.x) {
+        const int s = find_segment(segs, n_segs, b, [](const DevSeg& g) { return g.item_prefix; });
+        const DevSeg& sg = segs[s];
+        const NItem it = static_cast<const NItem*>(sg.items)[sg.item_begin + (b - sg.item_prefix)];
+        const DevUnit u = sg.units[it.unit];
+        const double* __restrict__ phi = static_cast<const double*>(sg.phi) + u.out_offset;
+        const int32_t* __restrict__ fn = sg.unit_fn + u.fn_begin;
+        const double* __restrict__ D = sg.D;
+        const int64_t ldd = sg.ld;
+        const int np = u.n_points, ld = u.ld, m = u.m;
+        const int P = (np + 15) >> 4;
+        const int J0 = it.tj * TILE;
+        const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+        const int lr = lane & 15, lk = lane >> 4;
 
-    d4 acc[MAX_UNIT_POINTS / 16];
-#pragma unroll
-    for (int i = 0; i < MAX_UNIT_POINTS / 16; ++i) acc[i] = d4{0.0, 0.0, 0.0, 0.0};
+        d4 acc[MAX_UNIT_POINTS / 16];
+    #pragma unroll
+        for (int i = 0; i < MAX_UNIT_POINTS / 16; ++i) acc[i] = d4{0.0, 0.0, 0.0, 0.0};
 
-    for (int ti = 0; ti <= it.tj; ++ti) {
-        const bool diag = ti == it.tj;
-        for (int i0 = 0; i0 < TILE; i0 += KCHUNK) {
-            const int c0 = ti * TILE + i0;
-            for (int e = tid; e < MAX_UNIT_POINTS * KCHUNK; e += 256) {
-                const int p = e >> 4, i = e & 15;
-                As[p][i] = p < np ? phi[(int64_t)p * ld + c0 + i] : 0.0;
-            }
-#pragma unroll
-            for (int e = tid; e < KCHUNK * TILE; e += 256) {
-                const int i = e >> 6, j = e & 63;
-                const int ci = c0 + i, cj = J0 + j;
-                double val = 0.0;
-                if (ci < m && cj < m) {
-                    const int64_t gi = fn[ci], gj = fn[cj];
-                    if (!diag) val = 2.0 * D[gi * ldd + gj];
-                    else val = ci <= cj ? D[gi * ldd + gj] : D[gj * ldd + gi];
+        for (int ti = 0; ti <= it.tj; ++ti) {
+            const bool diag = ti == it.tj;
+            for (int i0 = 0; i0 < TILE; i0 += KCHUNK) {
+                const int c0 = ti * TILE + i0;
+                for (int e = tid; e < MAX_UNIT_POINTS * KCHUNK; e += 256) {
+                    const int p = e >> 4, i = e & 15;
+                    As[p][i] = p < np ? phi[(int64_t)p * ld + c0 + i] : 0.0;
                 }
-                Bs[i][j] = val;
-            }
-            __syncthreads();
-#pragma unroll
-            for (int kk = 0; kk < KCHUNK / 4; ++kk) {
-                const double bv = Bs[kk * 4 + lk][wave * 16 + lr];
-#pragma unroll
-                for (int pb = 0; pb < MAX_UNIT_POINTS / 16; ++pb)
-                    if (pb < P) {
-                        const double av = As[pb * 16 + lr][kk * 4 + lk];
-                        acc[pb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[pb], 0, 0, 0);
+    #pragma unroll
+                for (int e = tid; e < KCHUNK * TILE; e += 256) {
+                    const int i = e >> 6, j = e & 63;
+                    const int ci = c0 + i, cj = J0 + j;
+                    double val = 0.0;
+                    if (ci < m && cj < m) {
+                        const int64_t gi = fn[ci], gj = fn[cj];
+                        if (!diag) val = 2.0 * D[gi * ldd + gj];
+                        else val = ci <= cj ? D[gi * ldd + gj] : D[gj * ldd + gi];
                     }
+                    Bs[i][j] = val;
+                }
+                __syncthreads();
+    #pragma unroll
+                for (int kk = 0; kk < KCHUNK / 4; ++kk) {
+                    const double bv = Bs[kk * 4 + lk][wave * 16 + lr];
+    #pragma unroll
+                    for (int pb = 0; pb < MAX_UNIT_POINTS / 16; ++pb)
+                        if (pb < P) {
+                            const double av = As[pb * 16 + lr][kk * 4 + lk];
+                            acc[pb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[pb], 0, 0, 0);
+                        }
+                }
+                __syncthreads();
             }
-            __syncthreads();
         }
-    }
 
-    const int cj = J0 + wave * 16 + lr;
-#pragma unroll
-    for (int pb = 0; pb < MAX_UNIT_POINTS / 16; ++pb) {
-        if (pb < P) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int p = pb * 16 + lk * 4 + r;
-                double v = 0.0;
-                if (p < np && cj < m) v = acc[pb][r] * phi[(int64_t)p * ld + cj];
-                v += __shfl_xor(v, 1);
-                v += __shfl_xor(v, 2);
-                v += __shfl_xor(v, 4);
-                v += __shfl_xor(v, 8);
-                if (lr == 0) red[wave][p] = v;
+        const int cj = J0 + wave * 16 + lr;
+    #pragma unroll
+        for (int pb = 0; pb < MAX_UNIT_POINTS / 16; ++pb) {
+            if (pb < P) {
+    #pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int p = pb * 16 + lk * 4 + r;
+                    double v = 0.0;
+                    if (p < np && cj < m) v = acc[pb][r] * phi[(int64_t)p * ld + cj];
+                    v += __shfl_xor(v, 1);
+                    v += __shfl_xor(v, 2);
+                    v += __shfl_xor(v, 4);
+                    v += __shfl_xor(v, 8);
+                    if (lr == 0) red[wave][p] = v;
+                }
             }
         }
-    }
-    __syncthreads();
-    if (tid < np) {
-        const double v = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
-        const int64_t pc = sg.sys->perm[u.point_begin + tid];
-        unsafeAtomicAdd(sg.n + pc, v);
+        __syncthreads();
+        if (tid < np) {
+            const double v = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
+            const int64_t pc = sg.sys->perm[u.point_begin + tid];
+            unsafeAtomicAdd(sg.n + pc, v);
+        }
     }
 }
 
-hipError_t launch_n_f64(const DevSeg* segs_dev, int n_segs, int64_t n_items, hipStream_t st)
+
+// ------------------------------------------------------------------------------------------
+// Reduced-precision contractions.  Basis values arrive as FP32 (rounded from the FP64
+// evaluation); w*v and D are rounded from FP64 when staged.  Per-tile results are flushed
+// into FP64 accumulators and reach H and n through FP64 atomics.
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+// Hamiltonian, FP32 MFMA (v_mfma_f32_16x16x4f32), same tiling as the FP64 kernel.
+__global__ __launch_bounds__(256) void h_kernel_f32(const DevSeg* __restrict__ segs, int n_segs, int64_t total)
+{
+    __shared__ float As[KCHUNK][TILE + 4];
+    __shared__ float Bs[KCHUNK][TILE + 4];
+    for (int64_t b = blockIdx.x; b < total; b += gridDim.x) {
+        const int s = find_segment(segs, n_segs, b, [](const DevSeg& g) { return g.item_prefix; });
+        const DevSeg& sg = segs[s];
+        const HItem it = static_cast<const HItem*>(sg.items)[sg.item_begin + (b - sg.item_prefix)];
+        const DevUnit u = sg.units[it.unit];
+        const float* __restrict__ phi = static_cast<const float*>(sg.phi) + u.out_offset;
+        const double* __restrict__ wv = sg.wv + u.point_begin;
+        const int np = u.n_points, ld = u.ld;
+        const int I0 = it.ti * TILE, J0 = it.tj * TILE;
+        const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+        const int wr = wave >> 1, wc = wave & 1;
+        const int lr = lane & 15, lk = lane >> 4;
+        f4 acc[2][2];
+    #pragma unroll
+        for (int i = 0; i < 2; ++i)
+    #pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+        for (int k0 = 0; k0 < np; k0 += KCHUNK) {
+    #pragma unroll
+            for (int e = tid; e < KCHUNK * TILE; e += 256) {
+                const int r = e >> 6, c = e & 63;
+                const int p = k0 + r;
+                float a = 0.f, bb = 0.f;
+                if (p < np) {
+                    const float* rowp = phi + (int64_t)p * ld;
+                    a = (float)((double)rowp[I0 + c] * wv[p]);
+                    bb = rowp[J0 + c];
+                }
+                As[r][c] = a;
+                Bs[r][c] = bb;
+            }
+            __syncthreads();
+    #pragma unroll
+            for (int kk = 0; kk < KCHUNK / 4; ++kk) {
+                const int kr = kk * 4 + lk;
+                const float a0 = As[kr][wr * 32 + lr], a1 = As[kr][wr * 32 + 16 + lr];
+                const float b0 = Bs[kr][wc * 32 + lr], b1 = Bs[kr][wc * 32 + 16 + lr];
+                acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
+                acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
+                acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
+                acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
+            }
+            __syncthreads();
+        }
+        const int32_t* __restrict__ fn = sg.unit_fn + u.fn_begin;
+        const bool diag = it.ti == it.tj;
+    #pragma unroll
+        for (int ib = 0; ib < 2; ++ib)
+    #pragma unroll
+            for (int jb = 0; jb < 2; ++jb)
+    #pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = wr * 32 + ib * 16 + lk * 4 + r, col = wc * 32 + jb * 16 + lr;
+                    const int ci = I0 + row, cj = J0 + col;
+                    if (ci < u.m && cj < u.m && (!diag || row <= col))
+                        unsafeAtomicAdd(sg.H + (int64_t)fn[ci] * sg.ld + fn[cj], (double)acc[ib][jb][r]);
+                }
+    }
+}
+
+// Density, FP32 MFMA; same tiling as the FP64 kernel, D rounded to FP32 when staged.
+__global__ __launch_bounds__(256) void n_kernel_f32(const DevSeg* __restrict__ segs, int n_segs, int64_t total)
+{
+    __shared__ float As[MAX_UNIT_POINTS][KCHUNK + 1];
+    __shared__ float Bs[KCHUNK][TILE + 4];
+    __shared__ double red[4][MAX_UNIT_POINTS];
+    for (int64_t b = blockIdx.x; b < total; b += gridDim.x) {
+        const int s = find_segment(segs, n_segs, b, [](const DevSeg& g) { return g.item_prefix; });
+        const DevSeg& sg = segs[s];
+        const NItem it = static_cast<const NItem*>(sg.items)[sg.item_begin + (b - sg.item_prefix)];
+        const DevUnit u = sg.units[it.unit];
+        const float* __restrict__ phi = static_cast<const float*>(sg.phi) + u.out_offset;
+        const int32_t* __restrict__ fn = sg.unit_fn + u.fn_begin;
+        const double* __restrict__ D = sg.D;
+        const int64_t ldd = sg.ld;
+        const int np = u.n_points, ld = u.ld, m = u.m;
+        const int P = (np + 15) >> 4;
+        const int J0 = it.tj * TILE;
+        const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+        const int lr = lane & 15, lk = lane >> 4;
+        f4 acc[MAX_UNIT_POINTS / 16];
+        d4 acc64[MAX_UNIT_POINTS / 16];
+    #pragma unroll
+        for (int i = 0; i < MAX_UNIT_POINTS / 16; ++i) {
+            acc[i] = f4{0.f, 0.f, 0.f, 0.f};
+            acc64[i] = d4{0.0, 0.0, 0.0, 0.0};
+        }
+        for (int ti = 0; ti <= it.tj; ++ti) {
+            const bool diag = ti == it.tj;
+            for (int i0 = 0; i0 < TILE; i0 += KCHUNK) {
+                const int c0 = ti * TILE + i0;
+                for (int e = tid; e < MAX_UNIT_POINTS * KCHUNK; e += 256) {
+                    const int p = e >> 4, i = e & 15;
+                    As[p][i] = p < np ? phi[(int64_t)p * ld + c0 + i] : 0.f;
+                }
+    #pragma unroll
+                for (int e = tid; e < KCHUNK * TILE; e += 256) {
+                    const int i = e >> 6, j = e & 63;
+                    const int ci = c0 + i, cj = J0 + j;
+                    double val = 0.0;
+                    if (ci < m && cj < m) {
+                        const int64_t gi = fn[ci], gj = fn[cj];
+                        if (!diag) val = 2.0 * D[gi * ldd + gj];
+                        else val = ci <= cj ? D[gi * ldd + gj] : D[gj * ldd + gi];
+                    }
+                    Bs[i][j] = (float)val;
+                }
+                __syncthreads();
+    #pragma unroll
+                for (int kk = 0; kk < KCHUNK / 4; ++kk) {
+                    const float bv = Bs[kk * 4 + lk][wave * 16 + lr];
+    #pragma unroll
+                    for (int pb = 0; pb < MAX_UNIT_POINTS / 16; ++pb)
+                        if (pb < P) acc[pb] = __builtin_amdgcn_mfma_f32_16x16x4f32(As[pb * 16 + lr][kk * 4 + lk], bv, acc[pb], 0, 0, 0);
+                }
+                __syncthreads();
+            }
+            // one 64-wide tile of D done: move the FP32 partial sums into FP64
+    #pragma unroll
+            for (int pb = 0; pb < MAX_UNIT_POINTS / 16; ++pb)
+    #pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    acc64[pb][r] += (double)acc[pb][r];
+                    acc[pb][r] = 0.f;
+                }
+        }
+        const int cj = J0 + wave * 16 + lr;
+    #pragma unroll
+        for (int pb = 0; pb < MAX_UNIT_POINTS / 16; ++pb) {
+            if (pb < P) {
+    #pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int p = pb * 16 + lk * 4 + r;
+                    double v = 0.0;
+                    if (p < np && cj < m) v = acc64[pb][r] * (double)phi[(int64_t)p * ld + cj];
+                    v += __shfl_xor(v, 1);
+                    v += __shfl_xor(v, 2);
+                    v += __shfl_xor(v, 4);
+                    v += __shfl_xor(v, 8);
+                    if (lr == 0) red[wave][p] = v;
+                }
+            }
+        }
+        __syncthreads();
+        if (tid < np) {
+            const double v = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
+            unsafeAtomicAdd(sg.n + sg.sys->perm[u.point_begin + tid], v);
+        }
+    }
+}
+
+// Split of an FP32 value into NS bf16 parts: x ~ x0 + x1 (+ x2), each part the rounding to
+// nearest of what the previous parts leave.
+template <int NS>
+__device__ inline void split_bf16(float x, __bf16* part)
+{
+    float r = x;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const __bf16 h = (__bf16)r;
+        part[s] = h;
+        r -= (float)h;
+    }
+}
+
+// Products kept: parts (s, t) with s + t <= NS - 1 (3 terms for NS = 2, 6 terms for NS = 3).
+template <int NS>
+__device__ inline f4 mfma_split(const bf8* a, const bf8* b, f4 acc)
+{
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+#pragma unroll
+        for (int t = 0; t < NS; ++t)
+            if (s + t <= NS - 1) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[s], b[t], acc, 0, 0, 0);
+    return acc;
+}
+
+constexpr int BK = 32;      // K per bf16 MFMA step
+constexpr int BKP = BK + 8;  // padded LDS row (80 bytes: keeps 16-byte alignment)
+
+// Hamiltonian, split-BF16 MFMA (v_mfma_f32_16x16x32_bf16): K = 32 points per step; LDS holds
+// [part][column][point] so every lane reads its 8 consecutive points as one 16-byte vector.
+template <int NS>
+__global__ __launch_bounds__(256) void h_kernel_bf16(const DevSeg* __restrict__ segs, int n_segs, int64_t total)
+{
+    __shared__ __attribute__((aligned(16))) __bf16 As[NS][TILE][BKP];
+    __shared__ __attribute__((aligned(16))) __bf16 Bs[NS][TILE][BKP];
+    for (int64_t b = blockIdx.x; b < total; b += gridDim.x) {
+        const int s = find_segment(segs, n_segs, b, [](const DevSeg& g) { return g.item_prefix; });
+        const DevSeg& sg = segs[s];
+        const HItem it = static_cast<const HItem*>(sg.items)[sg.item_begin + (b - sg.item_prefix)];
+        const DevUnit u = sg.units[it.unit];
+        const float* __restrict__ phi = static_cast<const float*>(sg.phi) + u.out_offset;
+        const double* __restrict__ wv = sg.wv + u.point_begin;
+        const int np = u.n_points, ld = u.ld;
+        const int I0 = it.ti * TILE, J0 = it.tj * TILE;
+        const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+        const int wr = wave >> 1, wc = wave & 1;
+        const int lr = lane & 15, lk = lane >> 4;
+        f4 acc[2][2];
+        d4 acc64[2][2];
+    #pragma unroll
+        for (int i = 0; i < 2; ++i)
+    #pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+                acc64[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+            }
+        for (int k0 = 0; k0 < np; k0 += BK) {
+    #pragma unroll
+            for (int e = tid; e < BK * TILE; e += 256) {
+                const int r = e >> 6, c = e & 63;
+                const int p = k0 + r;
+                float a = 0.f, bb = 0.f;
+                if (p < np) {
+                    const float* rowp = phi + (int64_t)p * ld;
+                    a = (float)((double)rowp[I0 + c] * wv[p]);
+                    bb = rowp[J0 + c];
+                }
+                __bf16 pa[NS], pb[NS];
+                split_bf16<NS>(a, pa);
+                split_bf16<NS>(bb, pb);
+    #pragma unroll
+                for (int q = 0; q < NS; ++q) {
+                    As[q][c][r] = pa[q];
+                    Bs[q][c][r] = pb[q];
+                }
+            }
+            __syncthreads();
+            bf8 a0[NS], a1[NS], b0[NS], b1[NS];
+    #pragma unroll
+            for (int q = 0; q < NS; ++q) {
+                a0[q] = *reinterpret_cast<const bf8*>(&As[q][wr * 32 + lr][lk * 8]);
+                a1[q] = *reinterpret_cast<const bf8*>(&As[q][wr * 32 + 16 + lr][lk * 8]);
+                b0[q] = *reinterpret_cast<const bf8*>(&Bs[q][wc * 32 + lr][lk * 8]);
+                b1[q] = *reinterpret_cast<const bf8*>(&Bs[q][wc * 32 + 16 + lr][lk * 8]);
+            }
+            acc[0][0] = mfma_split<NS>(a0, b0, acc[0][0]);
+            acc[0][1] = mfma_split<NS>(a0, b1, acc[0][1]);
+            acc[1][0] = mfma_split<NS>(a1, b0, acc[1][0]);
+            acc[1][1] = mfma_split<NS>(a1, b1, acc[1][1]);
+            __syncthreads();
+            // every 32 points: move the FP32 sums into FP64
+    #pragma unroll
+            for (int i = 0; i < 2; ++i)
+    #pragma unroll
+                for (int j = 0; j < 2; ++j)
+    #pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        acc64[i][j][r] += (double)acc[i][j][r];
+                        acc[i][j][r] = 0.f;
+                    }
+        }
+        const int32_t* __restrict__ fn = sg.unit_fn + u.fn_begin;
+        const bool diag = it.ti == it.tj;
+    #pragma unroll
+        for (int ib = 0; ib < 2; ++ib)
+    #pragma unroll
+            for (int jb = 0; jb < 2; ++jb)
+    #pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = wr * 32 + ib * 16 + lk * 4 + r, col = wc * 32 + jb * 16 + lr;
+                    const int ci = I0 + row, cj = J0 + col;
+                    if (ci < u.m && cj < u.m && (!diag || row <= col))
+                        unsafeAtomicAdd(sg.H + (int64_t)fn[ci] * sg.ld + fn[cj], acc64[ib][jb][r]);
+                }
+    }
+}
+
+// Density, split-BF16 MFMA: K = 32 functions per step.  A (points x functions) in LDS as
+// [part][point][function]; B (functions x columns) as [part][column][function].
+template <int NS>
+__global__ __launch_bounds__(256) void n_kernel_bf16(const DevSeg* __restrict__ segs, int n_segs, int64_t total)
+{
+    __shared__ __attribute__((aligned(16))) __bf16 As[NS][MAX_UNIT_POINTS][BKP];
+    __shared__ __attribute__((aligned(16))) __bf16 Bs[NS][TILE][BKP];
+    __shared__ double red[4][MAX_UNIT_POINTS];
+    for (int64_t b = blockIdx.x; b < total; b += gridDim.x) {
+        const int s = find_segment(segs, n_segs, b, [](const DevSeg& g) { return g.item_prefix; });
+        const DevSeg& sg = segs[s];
+        const NItem it = static_cast<const NItem*>(sg.items)[sg.item_begin + (b - sg.item_prefix)];
+        const DevUnit u = sg.units[it.unit];
+        const float* __restrict__ phi = static_cast<const float*>(sg.phi) + u.out_offset;
+        const int32_t* __restrict__ fn = sg.unit_fn + u.fn_begin;
+        const double* __restrict__ D = sg.D;
+        const int64_t ldd = sg.ld;
+        const int np = u.n_points, ld = u.ld, m = u.m;
+        const int P = (np + 15) >> 4;
+        const int J0 = it.tj * TILE;
+        const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+        const int lr = lane & 15, lk = lane >> 4;
+        f4 acc[MAX_UNIT_POINTS / 16];
+        d4 acc64[MAX_UNIT_POINTS / 16];
+    #pragma unroll
+        for (int i = 0; i < MAX_UNIT_POINTS / 16; ++i) {
+            acc[i] = f4{0.f, 0.f, 0.f, 0.f};
+            acc64[i] = d4{0.0, 0.0, 0.0, 0.0};
+        }
+        for (int ti = 0; ti <= it.tj; ++ti) {
+            const bool diag = ti == it.tj;
+            for (int i0 = 0; i0 < TILE; i0 += BK) {
+                const int c0 = ti * TILE + i0;
+                for (int e = tid; e < MAX_UNIT_POINTS * BK; e += 256) {
+                    const int p = e >> 5, i = e & 31;
+                    const float x = p < np ? phi[(int64_t)p * ld + c0 + i] : 0.f;
+                    __bf16 px[NS];
+                    split_bf16<NS>(x, px);
+    #pragma unroll
+                    for (int q = 0; q < NS; ++q) As[q][p][i] = px[q];
+                }
+                for (int e = tid; e < BK * TILE; e += 256) {
+                    const int i = e >> 6, j = e & 63;
+                    const int ci = c0 + i, cj = J0 + j;
+                    double val = 0.0;
+                    if (ci < m && cj < m) {
+                        const int64_t gi = fn[ci], gj = fn[cj];
+                        if (!diag) val = 2.0 * D[gi * ldd + gj];
+                        else val = ci <= cj ? D[gi * ldd + gj] : D[gj * ldd + gi];
+                    }
+                    __bf16 pv[NS];
+                    split_bf16<NS>((float)val, pv);
+    #pragma unroll
+                    for (int q = 0; q < NS; ++q) Bs[q][j][i] = pv[q];
+                }
+                __syncthreads();
+                bf8 bv[NS];
+    #pragma unroll
+                for (int q = 0; q < NS; ++q) bv[q] = *reinterpret_cast<const bf8*>(&Bs[q][wave * 16 + lr][lk * 8]);
+    #pragma unroll
+                for (int pb = 0; pb < MAX_UNIT_POINTS / 16; ++pb)
+                    if (pb < P) {
+                        bf8 av[NS];
+    #pragma unroll
+                        for (int q = 0; q < NS; ++q) av[q] = *reinterpret_cast<const bf8*>(&As[q][pb * 16 + lr][lk * 8]);
+                        acc[pb] = mfma_split<NS>(av, bv, acc[pb]);
+                    }
+                __syncthreads();
+            }
+    #pragma unroll
+            for (int pb = 0; pb < MAX_UNIT_POINTS / 16; ++pb)
+    #pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    acc64[pb][r] += (double)acc[pb][r];
+                    acc[pb][r] = 0.f;
+                }
+        }
+        const int cj = J0 + wave * 16 + lr;
+    #pragma unroll
+        for (int pb = 0; pb < MAX_UNIT_POINTS / 16; ++pb) {
+            if (pb < P) {
+    #pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int p = pb * 16 + lk * 4 + r;
+                    double v = 0.0;
+                    if (p < np && cj < m) v = acc64[pb][r] * (double)phi[(int64_t)p * ld + cj];
+                    v += __shfl_xor(v, 1);
+                    v += __shfl_xor(v, 2);
+                    v += __shfl_xor(v, 4);
+                    v += __shfl_xor(v, 8);
+                    if (lr == 0) red[wave][p] = v;
+                }
+            }
+        }
+        __syncthreads();
+        if (tid < np) {
+            const double v = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
+            unsafeAtomicAdd(sg.n + sg.sys->perm[u.point_begin + tid], v);
+        }
+    }
+}
+
+hipError_t launch_h(Mode mode, const DevSeg* segs_dev, int n_segs, int64_t n_items, hipStream_t st,
+                    int64_t max_grid)
 {
     if (n_items <= 0 || n_segs <= 0) return hipSuccess;
     if (n_items > 0x7fffffff) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(n_kernel_f64, dim3((unsigned)n_items), dim3(256), 0, st, segs_dev, n_segs);
+    const dim3 g(grid_for(n_items, max_grid)), b(256);
+    switch (mode) {
+    case MODE_FP64: hipLaunchKernelGGL(h_kernel_f64, g, b, 0, st, segs_dev, n_segs, n_items); break;
+    case MODE_FP32: hipLaunchKernelGGL(h_kernel_f32, g, b, 0, st, segs_dev, n_segs, n_items); break;
+    case MODE_BF16X3: hipLaunchKernelGGL(h_kernel_bf16<2>, g, b, 0, st, segs_dev, n_segs, n_items); break;
+    case MODE_BF16X6: hipLaunchKernelGGL(h_kernel_bf16<3>, g, b, 0, st, segs_dev, n_segs, n_items); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_n(Mode mode, const DevSeg* segs_dev, int n_segs, int64_t n_items, hipStream_t st,
+                    int64_t max_grid)
+{
+    if (n_items <= 0 || n_segs <= 0) return hipSuccess;
+    if (n_items > 0x7fffffff) return hipErrorInvalidValue;
+    const dim3 g(grid_for(n_items, max_grid)), b(256);
+    switch (mode) {
+    case MODE_FP64: hipLaunchKernelGGL(n_kernel_f64, g, b, 0, st, segs_dev, n_segs, n_items); break;
+    case MODE_FP32: hipLaunchKernelGGL(n_kernel_f32, g, b, 0, st, segs_dev, n_segs, n_items); break;
+    case MODE_BF16X3: hipLaunchKernelGGL(n_kernel_bf16<2>, g, b, 0, st, segs_dev, n_segs, n_items); break;
+    case MODE_BF16X6: hipLaunchKernelGGL(n_kernel_bf16<3>, g, b, 0, st, segs_dev, n_segs, n_items); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -12,6 +12,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include "devtypes.h"
+#include "internal.h"
 #include "nao.h"
 #include "plan.h"
 
@@ -52,6 +53,10 @@ struct nao_ctx_s {
     };
     std::vector<Rec> recs;
     std::vector<hipEvent_t> pool;
+    int n_cu = 256;
+    int64_t persistent_per_cu = 4;       // workgroups per CU of a multi-structure launch
+    std::vector<struct ManyPlan*> many;  // launch plans of nao_run_many (captured graphs)
+    std::vector<std::pair<hipEvent_t, struct ManyPlan*>> inflight;  // eager plans still running
 };
 
 namespace {
@@ -363,6 +368,292 @@ bool finite_all(const double* p, int64_t n)
 
 }  // namespace
 
+
+// ------------------------------------------------------------------------------------------
+// many structures per launch sequence
+
+static const char* kname(bool ham, nao_precision p)
+{
+    static const char* h[] = {"h_f64", "h_f32", "h_bf16x3", "h_bf16x6"};
+    static const char* n[] = {"n_f64", "n_f32", "n_bf16x3", "n_bf16x6"};
+    return ham ? h[p] : n[p];
+}
+
+
+struct ManyPlan {
+    std::vector<const void*> key;  // precision, then (sys, op, in, out) per entry
+    struct Chunk {
+        size_t all_off = 0, all_n = 0, h_off = 0, h_n = 0, n_off = 0, n_n = 0;
+        int64_t units = 0, h_items = 0, n_items = 0;
+    };
+    std::vector<Chunk> chunks;
+    std::vector<DevSeg> segs;
+    std::vector<nao_work> entries;
+    std::vector<int64_t> wv_off;  // per entry: offset into the w*v arena (H entries)
+    nao_precision prec = NAO_FP64;
+    DevArray d_segs, d_wv;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+void many_free(nao_ctx c, ManyPlan* m)
+{
+    if (m->exec) (void)hipGraphExecDestroy(m->exec);
+    if (m->graph) (void)hipGraphDestroy(m->graph);
+    dev_free(c, m->d_segs.p, m->d_segs.bytes);
+    dev_free(c, m->d_wv.p, m->d_wv.bytes);
+    delete m;
+}
+
+// Free eager launch plans whose work has finished (all of them when wait is set).
+void many_retire(nao_ctx c, bool wait)
+{
+    std::vector<std::pair<hipEvent_t, ManyPlan*>> keep;
+    for (auto& f : c->inflight) {
+        if (wait) (void)hipEventSynchronize(f.first);
+        if (wait || hipEventQuery(f.first) == hipSuccess) {
+            many_free(c, f.second);
+            c->pool.push_back(f.first);
+        } else {
+            keep.push_back(f);
+        }
+    }
+    c->inflight.swap(keep);
+}
+
+// Drop cached launch plans that mention sys (or all of them for sys = NULL).
+void many_forget(nao_ctx c, const nao_system_s* sys)
+{
+    (void)hipStreamSynchronize(c->stream);
+    many_retire(c, true);
+    std::vector<ManyPlan*> keep;
+    for (ManyPlan* m : c->many) {
+        bool uses = sys == nullptr;
+        for (const nao_work& w : m->entries) uses = uses || w.sys == sys;
+        if (uses) many_free(c, m);
+        else keep.push_back(m);
+    }
+    c->many.swap(keep);
+}
+
+nao_status many_build(nao_ctx c, const nao_work* work, int64_t n_work, nao_precision prec, ManyPlan* m)
+{
+    m->prec = prec;
+    m->entries.assign(work, work + n_work);
+    int64_t wv_total = 0;
+    for (const nao_work& w : m->entries) {
+        m->wv_off.push_back(wv_total);
+        if (w.op == 0) wv_total += w.sys->n_points;
+    }
+    nao_status st = ensure(c, m->d_wv, std::max<int64_t>(1, wv_total) * sizeof(double));
+    if (st != NAO_OK) return st;
+    // the scratch must hold the largest block of every system (systems may come from other
+    // contexts on this device)
+    int64_t need = 0;
+    for (const nao_work& w : m->entries)
+        for (const Block& b : w.sys->blocks) need = std::max(need, b.phi_elems);
+    if (need > (int64_t)c->scratch_elems) {
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        many_retire(c, true);
+        dev_free(c, c->scratch, c->scratch_elems * sizeof(double));
+        c->scratch = nullptr;
+        c->scratch_elems = 0;
+        void* p = nullptr;
+        if ((st = dev_alloc(c, (size_t)need * sizeof(double), &p)) != NAO_OK) return st;
+        c->scratch = static_cast<double*>(p);
+        c->scratch_elems = (size_t)need;
+    }
+    // one segment per (entry, block); consecutive segments share a chunk while their basis
+    // values fit the scratch
+    struct Pending { DevSeg g; bool ham; int64_t phi; };
+    std::vector<std::vector<Pending>> chunks(1);
+    int64_t off = 0;
+    for (size_t e = 0; e < m->entries.size(); ++e) {
+        const nao_work& w = m->entries[e];
+        nao_system_s* s = w.sys;
+        const bool ham = w.op == 0;
+        for (const Block& b : s->blocks) {
+            if (off + b.phi_elems > (int64_t)c->scratch_elems && off > 0) {
+                chunks.emplace_back();
+                off = 0;
+            }
+            DevSeg g = make_seg(s, b, ham);
+            if (ham) {
+                g.wv = m->d_wv.as<double>() + m->wv_off[e];
+                g.H = const_cast<double*>(w.out);
+            } else {
+                g.D = w.in;
+                g.n = w.out;
+            }
+            chunks.back().push_back(Pending{g, ham, off});
+            off += b.phi_elems;
+        }
+    }
+    const bool f32 = prec != NAO_FP64;
+    const size_t esz = f32 ? sizeof(float) : sizeof(double);
+    for (auto& ch : chunks) {
+        if (ch.empty()) continue;
+        ManyPlan::Chunk k;
+        k.all_off = m->segs.size();
+        for (Pending& p : ch) {
+            DevSeg g = p.g;
+            g.phi = static_cast<char*>(static_cast<void*>(c->scratch)) + p.phi * esz;
+            g.unit_prefix = k.units;
+            k.units += g.unit_count;
+            m->segs.push_back(g);
+        }
+        k.all_n = m->segs.size() - k.all_off;
+        for (int pass = 0; pass < 2; ++pass) {
+            const bool ham = pass == 0;
+            const size_t o = m->segs.size();
+            int64_t items = 0;
+            for (size_t q = 0; q < k.all_n; ++q) {
+                if (ch[q].ham != ham) continue;
+                DevSeg g = m->segs[k.all_off + q];
+                g.item_prefix = items;
+                items += g.item_count;
+                m->segs.push_back(g);
+            }
+            if (ham) {
+                k.h_off = o;
+                k.h_n = m->segs.size() - o;
+                k.h_items = items;
+            } else {
+                k.n_off = o;
+                k.n_n = m->segs.size() - o;
+                k.n_items = items;
+            }
+        }
+        m->chunks.push_back(k);
+    }
+    if ((st = upload(c, m->d_segs, m->segs.data(), std::max<size_t>(1, m->segs.size()) * sizeof(DevSeg))) != NAO_OK)
+        return st;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return NAO_OK;
+}
+
+nao_status many_enqueue(nao_ctx c, ManyPlan* m)
+{
+    const Mode mode = (Mode)m->prec;
+    const bool f32 = m->prec != NAO_FP64;
+    const int64_t grid = (int64_t)c->n_cu * c->persistent_per_cu;
+    for (size_t e = 0; e < m->entries.size(); ++e) {
+        const nao_work& w = m->entries[e];
+        nao_system_s* s = w.sys;
+        if (w.op == 0) {
+            LAUNCH(c, "fill", launch_fill(w.out, s->basis.n_basis * s->basis.n_basis, 0.0, c->stream));
+            LAUNCH(c, "wv", launch_wv(s->d_pw.as<double>(), s->d_perm.as<int32_t>(), w.in,
+                                      m->d_wv.as<double>() + m->wv_off[e], s->n_points, c->stream));
+        } else {
+            LAUNCH(c, "fill", launch_fill(w.out, s->n_points, 0.0, c->stream));
+        }
+    }
+    const DevSeg* d = m->d_segs.as<DevSeg>();
+    bool lds = true;
+    for (const nao_work& w : m->entries) lds = lds && w.sys->spline_lds;
+    for (const auto& k : m->chunks) {
+        LAUNCH(c, f32 ? "basis_f32" : "basis_f64",
+               launch_basis(d + k.all_off, (int)k.all_n, k.units, lds, f32, c->stream, grid));
+        if (k.h_n) LAUNCH(c, kname(true, m->prec), launch_h(mode, d + k.h_off, (int)k.h_n, k.h_items, c->stream, grid));
+        if (k.n_n) LAUNCH(c, kname(false, m->prec), launch_n(mode, d + k.n_off, (int)k.n_n, k.n_items, c->stream, grid));
+    }
+    for (const nao_work& w : m->entries)
+        if (w.op == 0) LAUNCH(c, "mirror", launch_mirror(w.out, w.sys->basis.n_basis, c->stream));
+    return NAO_OK;
+}
+
+nao_status run_many_impl(nao_ctx c, const nao_work* work, int64_t n_work, nao_precision prec, bool capture)
+{
+    many_retire(c, false);
+    std::vector<const void*> key;
+    key.push_back(reinterpret_cast<const void*>((uintptr_t)prec + 1));
+    for (int64_t k = 0; k < n_work; ++k) {
+        key.push_back(work[k].sys);
+        key.push_back(reinterpret_cast<const void*>((uintptr_t)work[k].op));
+        key.push_back(work[k].in);
+        key.push_back(work[k].out);
+    }
+    if (capture) {
+        for (ManyPlan* m : c->many)
+            if (m->key == key && m->exec) {
+                HIP_TRY(c, timed(c, "graph", [&]() { return hipGraphLaunch(m->exec, c->stream); }));
+                return NAO_OK;
+            }
+    }
+    ManyPlan* m = new ManyPlan();
+    m->key = key;
+    nao_status st = many_build(c, work, n_work, prec, m);
+    if (st != NAO_OK) {
+        many_free(c, m);
+        return st;
+    }
+    if (!capture) {
+        st = many_enqueue(c, m);
+        if (st != NAO_OK) {
+            (void)hipStreamSynchronize(c->stream);
+            many_free(c, m);
+            return st;
+        }
+        // the plan's device arrays must outlive the enqueued work: retire it once its event fires
+        hipEvent_t ev = take_event(c);
+        if (!ev) {
+            (void)hipStreamSynchronize(c->stream);
+            many_free(c, m);
+            return NAO_OK;
+        }
+        HIP_TRY(c, hipEventRecord(ev, c->stream));
+        c->inflight.push_back({ev, m});
+        return NAO_OK;
+    }
+    const bool prof = c->prof;
+    c->prof = false;  // no event records inside a captured graph
+    hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        st = many_enqueue(c, m);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(c->stream, &g);
+        m->graph = g;
+        if (st == NAO_OK && e2 != hipSuccess) st = hip_fail(c, e2, "hipStreamEndCapture");
+        if (st == NAO_OK) {
+            e = hipGraphInstantiate(&m->exec, m->graph, nullptr, nullptr, 0);
+            if (e != hipSuccess) st = hip_fail(c, e, "hipGraphInstantiate");
+        }
+    } else {
+        st = hip_fail(c, e, "hipStreamBeginCapture");
+    }
+    c->prof = prof;
+    if (st != NAO_OK) {
+        many_free(c, m);
+        return st;
+    }
+    if (c->many.size() >= 8) {
+        (void)hipStreamSynchronize(c->stream);
+        many_free(c, c->many.front());
+        c->many.erase(c->many.begin());
+    }
+    c->many.push_back(m);
+    HIP_TRY(c, timed(c, "graph", [&]() { return hipGraphLaunch(m->exec, c->stream); }));
+    return NAO_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------------------------
+// helpers for the serving core
+
+namespace nao {
+
+nao_status ctx_alloc(nao_ctx c, size_t bytes, void** out) { return dev_alloc(c, bytes, out); }
+void ctx_free(nao_ctx c, void* p, size_t bytes) { dev_free(c, p, bytes); }
+hipStream_t ctx_stream(nao_ctx c) { return c->stream; }
+int ctx_device(nao_ctx c) { return c->device; }
+void ctx_set_error(nao_ctx c, const std::string& msg) { set_err(c, msg); }
+size_t system_device_bytes(nao_system s) { return system_bytes(s); }
+
+}  // namespace nao
+
 // ------------------------------------------------------------------------------------------
 // C ABI
 
@@ -390,6 +681,15 @@ nao_status nao_ctx_create(int device, void* hip_stream, size_t hbm_budget_bytes,
     if (!c) return NAO_ERR_OUT_OF_MEMORY;
     c->device = device;
     c->budget = hbm_budget_bytes;
+    {
+        int cu = 0;
+        if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cu > 0)
+            c->n_cu = cu;
+    }
+    if (const char* e = std::getenv("NAO_PERSISTENT_PER_CU")) {
+        const long v = std::atol(e);
+        if (v >= 1 && v <= 64) c->persistent_per_cu = v;
+    }
     c->scratch_cap_elems = scratch_cap_from_env();
     e = hipSetDevice(device);
     if (e == hipSuccess) {
@@ -424,6 +724,7 @@ void nao_ctx_destroy(nao_ctx c)
 {
     if (!c) return;
     (void)hipSetDevice(c->device);
+    many_forget(c, nullptr);
     (void)hipStreamSynchronize(c->stream);
     dev_free(c, c->scratch, c->scratch_elems * sizeof(double));
     dev_free(c, c->wsum, (WSUM_BLOCKS + 1) * sizeof(double));
@@ -465,6 +766,7 @@ nao_status nao_ctx_synchronize(nao_ctx c)
     nao_status st = check_ctx(c);
     if (st != NAO_OK) return st;
     HIP_TRY(c, hipStreamSynchronize(c->stream));
+    many_retire(c, false);
     return NAO_OK;
 }
 
@@ -738,6 +1040,7 @@ nao_status nao_system_set_group_max(nao_system s, int32_t group_max)
     if (group_max < 16 || group_max > MAX_UNIT_POINTS)
         return (set_err(s->ctx, "group_max outside [16, 256]"), NAO_ERR_INVALID_ARG);
     HIP_TRY(s->ctx, hipStreamSynchronize(s->ctx->stream));
+    many_forget(s->ctx, s);
     s->group_max = group_max;
     try {
         return build_groups(s);
@@ -794,6 +1097,7 @@ void nao_system_destroy(nao_system s)
 {
     if (!s) return;
     (void)hipSetDevice(s->ctx->device);
+    many_forget(s->ctx, s);
     (void)hipStreamSynchronize(s->ctx->stream);
     free_all(s);
     s->ctx->n_systems--;
@@ -862,7 +1166,7 @@ nao_status nao_eval_basis(nao_system s, int64_t b0, int64_t b1, double* phi, nao
     g.unit_count = (int64_t)du.size();
     g.unit_prefix = 0;
     if ((st = upload(c, t_seg, &g, sizeof(DevSeg))) != NAO_OK) return cleanup(), st;
-    hipError_t e = launch_basis_f64(t_seg.as<DevSeg>(), 1, (int64_t)du.size(), s->spline_lds, c->stream);
+    hipError_t e = launch_basis(t_seg.as<DevSeg>(), 1, (int64_t)du.size(), s->spline_lds, false, c->stream);
     if (e == hipSuccess && phi_space == NAO_MEM_HOST)
         e = hipMemcpyAsync(phi, out, (size_t)total * sizeof(double), hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -875,14 +1179,15 @@ nao_status nao_eval_basis(nao_system s, int64_t b0, int64_t b1, double* phi, nao
 
 static nao_status check_prec(nao_ctx c, nao_precision p)
 {
-    if (p == NAO_FP64) return NAO_OK;
-    if (p == NAO_FP32 || p == NAO_BF16X3 || p == NAO_BF16X6)
-        return (set_err(c, "this precision is not available in this build"), NAO_ERR_INVALID_ARG);
+    if (p == NAO_FP64 || p == NAO_FP32 || p == NAO_BF16X3 || p == NAO_BF16X6) return NAO_OK;
     return (set_err(c, "unknown precision"), NAO_ERR_INVALID_ARG);
 }
 
-static nao_status run_blocks(nao_system s, bool ham, const double* wv, const double* D, double* H, double* n)
+static nao_status run_blocks(nao_system s, bool ham, nao_precision prec, const double* wv, const double* D, double* H,
+                             double* n)
 {
+    const Mode mode = (Mode)prec;
+    const bool f32 = prec != NAO_FP64;
     nao_ctx c = s->ctx;
     std::vector<DevSeg> segs;
     for (const Block& b : s->blocks) {
@@ -898,11 +1203,12 @@ static nao_status run_blocks(nao_system s, bool ham, const double* wv, const dou
                               c->stream));
     DevSeg* dseg = s->d_segs.as<DevSeg>();
     for (size_t k = 0; k < segs.size(); ++k) {
-        LAUNCH(c, "basis_f64", launch_basis_f64(dseg + k, 1, segs[k].unit_count, s->spline_lds, c->stream));
+        LAUNCH(c, f32 ? "basis_f32" : "basis_f64",
+               launch_basis(dseg + k, 1, segs[k].unit_count, s->spline_lds, f32, c->stream));
         if (ham)
-            LAUNCH(c, "h_f64", launch_h_f64(dseg + k, 1, segs[k].item_count, c->stream));
+            LAUNCH(c, kname(true, prec), launch_h(mode, dseg + k, 1, segs[k].item_count, c->stream));
         else
-            LAUNCH(c, "n_f64", launch_n_f64(dseg + k, 1, segs[k].item_count, c->stream));
+            LAUNCH(c, kname(false, prec), launch_n(mode, dseg + k, 1, segs[k].item_count, c->stream));
     }
     return NAO_OK;
 }
@@ -932,7 +1238,7 @@ nao_status nao_integrate_h(nao_system s, const double* v, nao_memspace v_space, 
     }
     LAUNCH(c, "fill", launch_fill(Hd, nb * nb, 0.0, c->stream));
     LAUNCH(c, "wv", launch_wv(s->d_pw.as<double>(), s->d_perm.as<int32_t>(), vd, s->d_wv.as<double>(), n, c->stream));
-    if ((st = run_blocks(s, true, s->d_wv.as<double>(), nullptr, Hd, nullptr)) != NAO_OK) return st;
+    if ((st = run_blocks(s, true, prec, s->d_wv.as<double>(), nullptr, Hd, nullptr)) != NAO_OK) return st;
     LAUNCH(c, "mirror", launch_mirror(Hd, nb, c->stream));
     if (H_space == NAO_MEM_HOST) {
         HIP_TRY(c, hipMemcpyAsync(H, Hd, nb * nb * sizeof(double), hipMemcpyDeviceToHost, c->stream));
@@ -966,7 +1272,7 @@ nao_status nao_update_density(nao_system s, const double* D, nao_memspace D_spac
         nd = s->d_n.as<double>();
     }
     LAUNCH(c, "fill", launch_fill(nd, n, 0.0, c->stream));
-    if ((st = run_blocks(s, false, nullptr, Dd, nullptr, nd)) != NAO_OK) return st;
+    if ((st = run_blocks(s, false, prec, nullptr, Dd, nullptr, nd)) != NAO_OK) return st;
     if (n_electrons) {
         LAUNCH(c, "electron_count", launch_weighted_sum(s->d_pw.as<double>(), s->d_perm.as<int32_t>(), nd, n,
                                                          c->wsum, c->wsum + WSUM_BLOCKS, c->stream));
@@ -981,12 +1287,28 @@ nao_status nao_update_density(nao_system s, const double* D, nao_memspace D_spac
 
 nao_status nao_run_many(nao_ctx c, const nao_work* work, int64_t n_work, nao_precision prec, uint32_t flags)
 {
-    (void)work;
-    (void)n_work;
-    (void)prec;
-    (void)flags;
-    set_err(c, "nao_run_many is not available in this build");
-    return NAO_ERR_NOT_READY;
+    nao_status st = check_ctx(c);
+    if (st != NAO_OK) return st;
+    if ((st = check_prec(c, prec)) != NAO_OK) return st;
+    if (n_work < 0 || (n_work > 0 && !work)) return (set_err(c, "bad work list"), NAO_ERR_INVALID_ARG);
+    if (flags & ~NAO_RUN_CAPTURE_GRAPH) return (set_err(c, "unknown flags"), NAO_ERR_INVALID_ARG);
+    for (int64_t k = 0; k < n_work; ++k) {
+        const nao_work& w = work[k];
+        if (!w.sys || w.sys->ctx->device != c->device)
+            return (set_err(c, "work entry with a system on another device"), NAO_ERR_INVALID_ARG);
+        if ((flags & NAO_RUN_CAPTURE_GRAPH) && w.sys->ctx != c)
+            return (set_err(c, "graph capture needs every system to belong to the context"), NAO_ERR_INVALID_ARG);
+        if (w.op != 0 && w.op != 1) return (set_err(c, "work op must be 0 (H) or 1 (density)"), NAO_ERR_INVALID_ARG);
+        const bool need_in = w.op == 0 ? w.sys->n_points > 0 : w.sys->basis.n_basis > 0;
+        if ((need_in && !w.in) || !w.out) return (set_err(c, "NULL work pointer"), NAO_ERR_INVALID_ARG);
+    }
+    if (n_work == 0) return NAO_OK;
+    try {
+        return run_many_impl(c, work, n_work, prec, (flags & NAO_RUN_CAPTURE_GRAPH) != 0);
+    } catch (const std::bad_alloc&) {
+        set_err(c, "host allocation failed");
+        return NAO_ERR_OUT_OF_MEMORY;
+    }
 }
 
 }  // extern "C"

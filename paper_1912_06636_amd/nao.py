@@ -81,13 +81,26 @@ _sig("nao_integrate_h", _S, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_
 _sig("nao_update_density", _S, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int, _c_dp)
 _sig("nao_system_destroy", None, _vp)
 _sig("nao_run_many", _S, _vp, ctypes.POINTER(Work), ctypes.c_int64, ctypes.c_int, ctypes.c_uint32)
+_sig("nao_server_create", _S, _vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int, ctypes.POINTER(_vp))
+_sig("nao_server_open_session", _S, _vp, ctypes.POINTER(BasisDesc), ctypes.c_int64, _c_dp, _c_dp, ctypes.c_int32,
+     _c_i64p)
+_sig("nao_server_close_session", _S, _vp, ctypes.c_int64)
+_sig("nao_server_session_info", _S, _vp, ctypes.c_int64, _c_i32p, ctypes.POINTER(ctypes.c_size_t), _c_i64p, _c_i64p)
+_sig("nao_server_submit", _S, _vp, ctypes.c_int64, _vp, ctypes.c_int, _vp, ctypes.c_int,
+     ctypes.POINTER(ctypes.c_uint64))
+_sig("nao_server_step", _S, _vp, _c_i32p, _c_i32p)
+_sig("nao_server_poll", _S, _vp, ctypes.c_uint64, _c_i32p, _c_dp, _c_dp, _c_dp)
+_sig("nao_server_result", _S, _vp, ctypes.c_uint64, _vp, _vp, ctypes.c_int)
+_sig("nao_server_destroy", None, _vp)
 
 EXPORTED = [
     "nao_ctx_create", "nao_ctx_destroy", "nao_last_error", "nao_ctx_set_stream", "nao_ctx_stream",
     "nao_ctx_synchronize", "nao_ctx_memory", "nao_ctx_profile", "nao_ctx_profile_read", "nao_plan_create", "nao_plan_info", "nao_plan_get_batches",
     "nao_plan_destroy", "nao_build_batches", "nao_system_set_group_max", "nao_system_info", "nao_get_batches",
     "nao_system_work", "nao_eval_basis", "nao_integrate_h", "nao_update_density", "nao_system_destroy",
-    "nao_run_many",
+    "nao_run_many", "nao_server_create", "nao_server_open_session", "nao_server_close_session",
+    "nao_server_session_info", "nao_server_submit", "nao_server_step", "nao_server_poll", "nao_server_result",
+    "nao_server_destroy",
 ]
 
 
@@ -327,3 +340,85 @@ class System:
         _check(_lib.nao_update_density(self.handle, pd, sd, PRECISIONS[precision], pn, sn,
                                        ctypes.byref(ne) if electrons else None), self.ctx.handle)
         return (out, ne.value) if electrons else out
+
+
+# ---------------------------------------------------------------------------------------------
+# serving core
+
+REQ_WAITING, REQ_RUNNING, REQ_DONE = 0, 1, 2
+
+
+class Server:
+    """nao_server: sessions admitted by the home context's HBM budget, n_slots stream slots,
+    continuous batching of (density, Hamiltonian) iteration requests."""
+
+    def __init__(self, home, n_slots=2, max_per_launch=8, precision="fp64"):
+        h = _vp()
+        _check(_lib.nao_server_create(home.handle, int(n_slots), int(max_per_launch), PRECISIONS[precision],
+                                      ctypes.byref(h)), home.handle)
+        self.home = home
+        self.handle = h
+        self._keep = {}
+
+    def close(self):
+        if self.handle:
+            _lib.nao_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def open_session(self, basis, xyz, w, max_batch):
+        d = _Desc(basis)
+        xyz = _f64(xyz).reshape(-1, 3)
+        w = _f64(w)
+        sid = ctypes.c_int64()
+        _check(_lib.nao_server_open_session(self.handle, ctypes.byref(d.struct), len(xyz), _p(xyz, _c_dp),
+                                            _p(w, _c_dp), int(max_batch), ctypes.byref(sid)), self.home.handle)
+        return sid.value
+
+    def close_session(self, sid):
+        _check(_lib.nao_server_close_session(self.handle, int(sid)), self.home.handle)
+
+    def session_info(self, sid):
+        r, b, nb, npt = ctypes.c_int32(), ctypes.c_size_t(), ctypes.c_int64(), ctypes.c_int64()
+        _check(_lib.nao_server_session_info(self.handle, int(sid), ctypes.byref(r), ctypes.byref(b), ctypes.byref(nb),
+                                            ctypes.byref(npt)), self.home.handle)
+        return dict(resident=bool(r.value), bytes=b.value, n_basis=nb.value, n_points=npt.value)
+
+    def submit(self, sid, D, v=None):
+        """Queue one iteration; D (and v) must stay valid until the request is done."""
+        pd, sd, kd = _ptr_space(D)
+        if v is not None:
+            pv, sv, kv = _ptr_space(v)
+        else:
+            pv, sv, kv = None, MEM_HOST, None
+        tk = ctypes.c_uint64()
+        _check(_lib.nao_server_submit(self.handle, int(sid), pd, sd, pv, sv, ctypes.byref(tk)), self.home.handle)
+        self._keep[tk.value] = (kd, kv)
+        return tk.value
+
+    def step(self):
+        r, w = ctypes.c_int32(), ctypes.c_int32()
+        _check(_lib.nao_server_step(self.handle, ctypes.byref(r), ctypes.byref(w)), self.home.handle)
+        return r.value, w.value
+
+    def poll(self, ticket):
+        st = ctypes.c_int32()
+        a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        _check(_lib.nao_server_poll(self.handle, int(ticket), ctypes.byref(st), ctypes.byref(a), ctypes.byref(b),
+                                    ctypes.byref(c)), self.home.handle)
+        if st.value == REQ_DONE:
+            self._keep.pop(int(ticket), None)
+        return st.value, a.value, b.value, c.value
+
+    def result(self, ticket, H=None, n=None):
+        ph, sh, kh = _ptr_space(H) if H is not None else (None, MEM_HOST, None)
+        pn, sn, kn = _ptr_space(n) if n is not None else (None, sh, None)
+        if H is not None and n is not None and sh != sn:
+            raise ValueError("H and n must be in the same memory space")
+        _check(_lib.nao_server_result(self.handle, int(ticket), ph, pn, sh if H is not None else sn),
+               self.home.handle)

@@ -1,0 +1,104 @@
+"""Many structures in one launch sequence (nao_run_many): each result equals the structure's
+own single-call result within FP64 summation-order tolerance, graph replays equal the eager
+launch on every replay, and the mixed list matches the oracle for one member."""
+import sys
+
+import numpy as np
+import pytest
+
+from tests.gpu_cases import case, rel_max
+from workloads import generate as g
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1912_06636_amd import nao
+    ctx = nao.Context(0)
+    structs = []
+    for k in range(5):   # config-3-like structures on a reduced 12 x 38 grid
+        xyz = g.geometry_sc_first_n([6, 11, 19, 27, 8][k], 2.2, 0.1, g.rng_for(3, 200 + k, 0))
+        p = dict(g.CONFIGS[3])
+        p.update(n_r=12, n_ang=38, n_gauss=8)
+        w = g.make_workload(xyz, p, 3, 200 + k, n_occ=2 * len(xyz))
+        s = nao.build_batches(ctx, w["basis"], w["xyz"], w["w"], w["max_batch"])
+        structs.append((w, s))
+    yield nao, ctx, structs, torch
+    for w, s in structs:
+        s.close()
+    ctx.close()
+
+
+def _tensors(torch, w, s):
+    dev = "cuda"
+    return (torch.from_numpy(w["v"]).to(dev), torch.from_numpy(w["D"]).to(dev),
+            torch.zeros((s.n_basis, s.n_basis), dtype=torch.float64, device=dev),
+            torch.zeros(s.n_points, dtype=torch.float64, device=dev))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("capture", [False, True])
+def test_many_equals_solo(env, prec, capture):
+    nao, ctx, structs, torch = env
+    say("run_many", prec, "capture", capture)
+    tens = [_tensors(torch, w, s) for w, s in structs]
+    work = []
+    for (w, s), (v, D, H, n) in zip(structs, tens):
+        work += [(s, "h", v, H), (s, "n", D, n)]
+    ctx.run_many(work, precision=prec, capture_graph=capture)
+    ctx.synchronize()
+    tol = 1e-12 if prec == "fp64" else 1e-6
+    for (w, s), (v, D, H, n) in zip(structs, tens):
+        Hs = s.integrate_h(w["v"], precision=prec)
+        ns = s.update_density(w["D"], precision=prec)
+        assert rel_max(H.cpu().numpy(), Hs) <= tol
+        assert rel_max(n.cpu().numpy(), ns) <= tol
+        assert np.array_equal(H.cpu().numpy(), H.cpu().numpy().T)
+
+
+def test_graph_replays_match_eager(env):
+    nao, ctx, structs, torch = env
+    say("graph replays")
+    tens = [_tensors(torch, w, s) for w, s in structs]
+    work = []
+    for (w, s), (v, D, H, n) in zip(structs, tens):
+        work += [(s, "h", v, H), (s, "n", D, n)]
+    ctx.run_many(work, capture_graph=False)
+    ctx.synchronize()
+    eager = [(H.cpu().numpy().copy(), n.cpu().numpy().copy()) for v, D, H, n in tens]
+    for rep in range(4):
+        for v, D, H, n in tens:      # the program's own work between replays
+            H.fill_(7.0)
+            n.fill_(-3.0)
+        torch.cuda.synchronize()
+        ctx.run_many(work, capture_graph=True)
+        ctx.synchronize()
+        for (He, ne), (v, D, H, n) in zip(eager, tens):
+            assert rel_max(H.cpu().numpy(), He) <= 1e-12, rep
+            assert rel_max(n.cpu().numpy(), ne) <= 1e-12, rep
+
+
+def test_many_matches_oracle_member(env):
+    """A known case mixed with other structures still matches the oracle."""
+    nao, ctx, structs, torch = env
+    w1, B, ref = case("multitile")
+    say("run_many oracle member")
+    s1 = nao.build_batches(ctx, w1["basis"], w1["xyz"], w1["w"], w1["max_batch"])
+    v1, D1, H1, n1 = _tensors(torch, w1, s1)
+    work = [(s1, "h", v1, H1), (s1, "n", D1, n1)]
+    for (w, s) in structs[:3]:
+        v, D, H, n = _tensors(torch, w, s)
+        work += [(s, "n", D, n), (s, "h", v, H)]
+    ctx.run_many(work, capture_graph=True)
+    ctx.synchronize()
+    assert rel_max(H1.cpu().numpy(), ref["H"]) <= 1e-12
+    assert rel_max(n1.cpu().numpy(), ref["n"]) <= 1e-12
+    s1.close()

@@ -200,3 +200,26 @@ def test_invalid_arguments_return_codes(nao, ctx):
     s = nao.build_batches(ctx, w["basis"], w["xyz"], w["w"], 200)
     assert rel_max(s.integrate_h(w["v"]), ref["H"]) <= TOL
     s.close()
+
+
+# Stated error bounds of the reduced-precision modes against the FP64 oracle (normwise max
+# relative error of H, n and N_e); the measured values are printed for the record.
+PREC_TOL = {"fp32": 1e-5, "bf16x3": 1e-4, "bf16x6": 1e-5}
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16x6"])
+@pytest.mark.parametrize("name", ["config1", "multitile"])
+def test_reduced_precision_error(nao, ctx, name, prec):
+    w, B, ref = case(name)
+    say("precision", prec, name)
+    s = nao.build_batches(ctx, w["basis"], w["xyz"], w["w"], w["max_batch"])
+    H = s.integrate_h(w["v"], precision=prec)
+    n, Ne = s.update_density(w["D"], precision=prec, electrons=True)
+    eH, en = rel_max(H, ref["H"]), rel_max(n, ref["n"])
+    eN = abs(Ne - ref["Ne"]) / abs(ref["Ne"])
+    say("precision", prec, name, "e_H %.3e e_n %.3e e_Ne %.3e" % (eH, en, eN))
+    assert np.array_equal(H, H.T)
+    assert np.all(n[ref["n"] == 0.0] == 0.0)
+    tol = PREC_TOL[prec]
+    assert eH <= tol and en <= tol and eN <= tol
+    s.close()
