@@ -94,6 +94,7 @@ typedef struct {
  * context allocates for all its systems (0 = no cap).  NAO_ERR_NOT_READY without a GPU.
  * ------------------------------------------------------------------------------------- */
 nao_status nao_ctx_create(int device, void* hip_stream, size_t hbm_budget_bytes, nao_ctx* out);
+/* Destroy every system and server of a context before the context itself. */
 void nao_ctx_destroy(nao_ctx ctx);
 /* Message of the last failing call on ctx; ctx = NULL gives the calling thread's last
  * message of a context-less call (nao_plan_*).  Never NULL; valid until the next call. */

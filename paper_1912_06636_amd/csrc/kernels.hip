@@ -208,6 +208,9 @@ hipError_t launch_basis(const DevSeg* segs_dev, int n_segs, int64_t n_units, boo
 //   H[I, J] += (w v Phi[:, I])^T Phi[:, J],
 // K loop over the unit's points in chunks of 16 staged in LDS; four waves, each a 32x32
 // quarter as 2x2 blocks of v_mfma_f64_16x16x4; FP64 atomics into the upper triangle.
+// Operand layouts of v_mfma_f64_16x16x4f64: A lane l holds A[l%16][l/16], B lane l holds
+// B[l/16][l%16]; the result register r of lane l is D[l/16 + 4r][l%16] (measured on gfx950;
+// the FP32 and BF16 16x16 instructions place it at D[4(l/16) + r][l%16] instead).
 
 __global__ __launch_bounds__(256) void h_kernel_f64(const DevSeg* __restrict__ segs, int n_segs, int64_t total)
 {
@@ -272,7 +275,7 @@ __global__ __launch_bounds__(256) void h_kernel_f64(const DevSeg* __restrict__ s
             for (int jb = 0; jb < 2; ++jb)
     #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int row = wr * 32 + ib * 16 + lk * 4 + r;
+                    const int row = wr * 32 + ib * 16 + lk + 4 * r;  // FP64 result layout
                     const int col = wc * 32 + jb * 16 + lr;
                     const int ci = I0 + row, cj = J0 + col;
                     if (ci < u.m && cj < u.m && (!diag || row <= col)) {
@@ -357,7 +360,7 @@ __global__ __launch_bounds__(256) void n_kernel_f64(const DevSeg* __restrict__ s
             if (pb < P) {
     #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int p = pb * 16 + lk * 4 + r;
+                    const int p = pb * 16 + lk + 4 * r;  // FP64 result layout
                     double v = 0.0;
                     if (p < np && cj < m) v = acc[pb][r] * phi[(int64_t)p * ld + cj];
                     v += __shfl_xor(v, 1);

@@ -10,6 +10,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import weakref
 
 import numpy as np
 
@@ -193,9 +194,12 @@ class Context:
         _check(_lib.nao_ctx_create(int(device), _vp(st) if st else None, int(hbm_budget), ctypes.byref(h)))
         self.handle = h
         self.device = device
+        self._children = weakref.WeakSet()  # systems and servers: destroyed before the context
 
     def close(self):
         if self.handle:
+            for ch in list(self._children):
+                ch.close()
             _lib.nao_ctx_destroy(self.handle)
             self.handle = None
 
@@ -269,13 +273,15 @@ class System:
                                       int(max_batch), ctypes.byref(h)), ctx.handle)
         self.ctx = ctx
         self.handle = h
+        ctx._children.add(self)
         self.n_points = len(xyz)
         info = self.info()
         self.n_basis, self.n_batches, self.n_list = info[0], info[1], info[2]
 
     def close(self):
         if self.handle:
-            _lib.nao_system_destroy(self.handle)
+            if self.ctx.handle:
+                _lib.nao_system_destroy(self.handle)
             self.handle = None
 
     def __del__(self):
@@ -359,10 +365,12 @@ class Server:
         self.home = home
         self.handle = h
         self._keep = {}
+        home._children.add(self)
 
     def close(self):
         if self.handle:
-            _lib.nao_server_destroy(self.handle)
+            if self.home.handle:
+                _lib.nao_server_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -1,0 +1,155 @@
+"""Poisson-arrival driver of the serving core (nao_server) and its latency report.
+
+Requests are SCF-iteration pairs (density update from a fresh density matrix, then the
+Hamiltonian with the structure's potential) for structures of 20-400 atoms shaped like the
+100-atom block or the 375-atom slab.  Sessions keep a structure resident for 10-40
+iterations; a request joins the oldest session with no request in flight, otherwise it opens
+a new session.  The structures come from a pool generated before the run; each iteration's
+density matrix D = C C^T (C seeded per session and iteration) is staged on the device before
+the request is submitted, and its staging time is reported separately.
+
+Two paths are compared:
+  * plain:   FP64, one request per launch, one slot, every octree batch its own unit;
+  * batched: split-BF16 (or another precision), several requests per launch, several slots,
+             execution groups of up to 256 points.
+"""
+from __future__ import annotations
+
+import math
+import time
+
+import numpy as np
+
+from workloads import generate as g
+
+
+def make_pool(n_structures, seed=0, min_atoms=20, max_atoms=400, grid_scale=1.0):
+    """Structures drawn log-uniformly in size, style 2 (block) or 4 (slab) by a coin flip."""
+    rng = g.rng_for(5, seed, g.STREAM_ARRIVAL)
+    pool = []
+    for k in range(n_structures):
+        n = int(round(math.exp(rng.uniform(math.log(min_atoms), math.log(max_atoms)))))
+        style = 2 if rng.uniform() < 0.5 else 4
+        xyz = g.serving_geometry(style, n, 1000 * seed + k)
+        p = dict(g.CONFIGS[style])
+        if grid_scale != 1.0:
+            p["n_r"] = max(8, int(p["n_r"] * grid_scale))
+            p["n_ang"] = max(14, int(p["n_ang"] * grid_scale))
+        w = g.make_workload(xyz, p, 5, 1000 * seed + k, with_density=False)
+        w["style"] = style
+        w["d_max"] = p["d_max"]
+        w["n_occ"] = 2 * len(xyz)
+        pool.append(w)
+    return pool
+
+
+class DensityStager:
+    """Fresh seeded D = C C^T per (session, iteration), built on the GPU with torch and zeroed
+    between centres farther apart than d_max (input staging, not part of the method)."""
+
+    def __init__(self, torch, device):
+        self.torch = torch
+        self.device = device
+        self.masks = {}
+
+    def make(self, work, session_seed, iteration):
+        torch = self.torch
+        key = id(work)
+        if key not in self.masks:
+            ba = g.basis_atom_index(work["basis"])
+            xyz = work["basis"]["atom_xyz"]
+            dd = np.sqrt(((xyz[:, None] - xyz[None]) ** 2).sum(-1))
+            keep = (dd <= work["d_max"])[ba][:, ba]
+            self.masks[key] = torch.from_numpy(keep).to(self.device)
+        gen = torch.Generator(device=self.device)
+        gen.manual_seed(int(session_seed) * 100003 + int(iteration))
+        C = torch.randn((work["n_basis"], work["n_occ"]), generator=gen, dtype=torch.float64, device=self.device)
+        D = C @ C.T
+        D = 0.5 * (D + D.T)
+        D.mul_(self.masks[key])
+        return D.contiguous()
+
+
+def run(nao, torch, pool, lam, duration_s, max_requests, path, precision="bf16x3", n_slots=3,
+        max_per_launch=8, hbm_budget=0, seed=0, log=None):
+    """One serving run; returns a dict with latency percentiles and throughput."""
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(np.random.SeedSequence([5, seed, g.STREAM_ARRIVAL, int(lam * 1000)]))
+    home = nao.Context(0, hbm_budget=hbm_budget)
+    if path == "plain":
+        srv = nao.Server(home, n_slots=1, max_per_launch=1, precision="fp64")
+    else:
+        srv = nao.Server(home, n_slots=n_slots, max_per_launch=max_per_launch, precision=precision)
+    stager = DensityStager(torch, dev)
+    sessions = []  # dicts: sid, work, k, K, busy, seed
+    tickets = {}   # ticket -> (session dict, t_arrival_wall)
+    lat, units_done, stage_s = [], 0.0, 0.0
+    done = 0
+    submitted = 0
+    t0 = time.perf_counter()
+    next_arrival = t0 + rng.exponential(1.0 / lam)
+    vbuf = {}
+    while True:
+        now = time.perf_counter()
+        if now - t0 > duration_s or done >= max_requests:
+            break
+        while now >= next_arrival and submitted < max_requests:
+            free = [s for s in sessions if not s["busy"] and s["k"] < s["K"]]
+            if free:
+                s = min(free, key=lambda x: x["opened"])
+            else:
+                w = pool[int(rng.integers(len(pool)))]
+                sid = srv.open_session(w["basis"], w["xyz"], w["w"], w["max_batch"])
+                s = dict(sid=sid, work=w, k=0, K=int(rng.integers(10, 41)), busy=False, opened=now,
+                         seed=len(sessions) + 1)
+                sessions.append(s)
+            ts = time.perf_counter()
+            D = stager.make(s["work"], s["seed"], s["k"])
+            torch.cuda.synchronize()
+            stage_s += time.perf_counter() - ts
+            v = None
+            if s["k"] == 0:
+                v = torch.from_numpy(s["work"]["v"]).to(dev)
+                torch.cuda.synchronize()
+                vbuf[s["sid"]] = v
+            tk = srv.submit(s["sid"], D, v)
+            tickets[tk] = (s, D)
+            s["busy"] = True
+            s["k"] += 1
+            submitted += 1
+            next_arrival += rng.exponential(1.0 / lam)
+        srv.step()
+        for tk in list(tickets):
+            st, t_sub, t_start, t_end = srv.poll(tk)
+            if st == nao.REQ_DONE:
+                s, _ = tickets.pop(tk)
+                s["busy"] = False
+                lat.append(t_end - t_sub)
+                done += 1
+                units_done += s["work"].get("units", 0.0)
+                if s["k"] >= s["K"]:
+                    srv.close_session(s["sid"])
+                    vbuf.pop(s["sid"], None)
+        time.sleep(0.0002)
+    elapsed = time.perf_counter() - t0
+    # drain what is still running so that the context can be torn down
+    t_drain = time.perf_counter()
+    while tickets and time.perf_counter() - t_drain < 120:
+        srv.step()
+        for tk in list(tickets):
+            if srv.poll(tk)[0] == nao.REQ_DONE:
+                tickets.pop(tk)
+        time.sleep(0.001)
+    srv.close()
+    home.close()
+    lat = np.array(lat) * 1e3
+    out = dict(path=path, precision="fp64" if path == "plain" else precision, lam=lam,
+               completed=int(done), submitted=int(submitted), seconds=round(elapsed, 2),
+               requests_per_s=round(done / elapsed, 3),
+               gpt_basis2_per_s=round(2.0 * units_done / elapsed / 1e9, 3),
+               p50_ms=round(float(np.percentile(lat, 50)), 2) if len(lat) else None,
+               p99_ms=round(float(np.percentile(lat, 99)), 2) if len(lat) else None,
+               staging_s=round(stage_s, 2), sessions=len(sessions))
+    if log:
+        log("serve %s" % out)
+    return out
