@@ -100,6 +100,8 @@ def main():
     ap.add_argument("--group-max", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--calibrate-copy", type=int, default=0,
+                    help="MiB copied once by a plain device copy (reference for counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the grid operations of one structure run on a single "
@@ -135,6 +137,15 @@ def main():
     def step():
         sysm.update_density(D, precision=args.precision, out=n)
         sysm.integrate_h(v, precision=args.precision, out=H)
+
+    if args.calibrate_copy:
+        nelem = args.calibrate_copy * (1 << 20) // 8
+        src = torch.ones(nelem, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("plain copy of %d MiB done" % args.calibrate_copy)
+        del src, dst
 
     for _ in range(args.warmup):
         step()

@@ -70,7 +70,8 @@ typedef enum { NAO_MEM_HOST = 0, NAO_MEM_DEVICE = 1 } nao_memspace;
  * global basis order is atom-major, then the species' shell order, then m = -l..l.
  * (Section "Computational Choices in FHI-aims": numeric atom-centred orbitals confined
  * to a cutoff radius; eq. EVNonPeriodic: the basis expansion.)
- * Constraints: 0 <= l <= 3, n_knots >= 4, 0 < rmin < rcut, finite samples.
+ * Constraints: 0 <= l <= 3, at most 16 shells per species, n_knots >= 4, 0 < rmin < rcut,
+ * finite samples.
  * ------------------------------------------------------------------------------------- */
 typedef struct {
     int64_t n_atoms;
@@ -154,8 +155,9 @@ void nao_plan_destroy(nao_plan plan);
 nao_status nao_build_batches(nao_ctx ctx, const nao_basis_desc* basis, int64_t n_points,
                              const double* point_xyz, const double* point_w, int32_t max_batch,
                              nao_system* out);
-/* Change the execution-group size (in points, 16..1024) of a system; results change only
- * by floating-point summation order. */
+/* Change the execution-group size (in points, 16..256; default 256) of a system; 0 runs
+ * every octree batch as its own unit (no packing).  Results change only by floating-point
+ * summation order. */
 nao_status nao_system_set_group_max(nao_system sys, int32_t group_max);
 nao_status nao_system_info(nao_system sys, int64_t* n_basis, int64_t* n_batches, int64_t* n_list,
                            size_t* dev_bytes);
@@ -246,8 +248,10 @@ typedef struct nao_server_s* nao_server;
 
 typedef enum { NAO_REQ_WAITING = 0, NAO_REQ_RUNNING = 1, NAO_REQ_DONE = 2 } nao_request_state;
 
-nao_status nao_server_create(nao_ctx home, int32_t n_slots, int32_t max_per_launch, nao_precision precision,
-                             nao_server* out);
+/* group_max: execution-group size of the sessions' systems (as nao_system_set_group_max;
+ * 0 = every octree batch its own unit). */
+nao_status nao_server_create(nao_ctx home, int32_t n_slots, int32_t max_per_launch, int32_t group_max,
+                             nao_precision precision, nao_server* out);
 /* Queue a structure (copied); returns its session id.  Admission happens in nao_server_step. */
 nao_status nao_server_open_session(nao_server srv, const nao_basis_desc* basis, int64_t n_points,
                                    const double* point_xyz, const double* point_w, int32_t max_batch,

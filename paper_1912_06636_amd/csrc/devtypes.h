@@ -26,6 +26,8 @@ struct DevSys {
     const int32_t* shell_radial;       // [n_shells]
     const double* radial_par;          // [n_radial][4]: rmin, rcut^2, 1/Delta, ln(rmin)
     const double* spline;              // [n_radial][n_knots-1][4] polynomial coefficients
+    const int32_t* species_fn_ptr;     // [n_species+1] into fn_code
+    const int32_t* fn_code;            // per species function: (shell within species << 4) | lm
     int32_t n_radial;
     int32_t n_knots;
     int64_t n_basis;
@@ -87,7 +89,9 @@ enum Mode { MODE_FP64 = 0, MODE_FP32 = 1, MODE_BF16X3 = 2, MODE_BF16X6 = 3 };
 
 // Basis values as FP64 (fp32_out = false) or rounded to FP32.
 // max_grid > 0 caps the grid: workgroups then loop over the items (persistent launch).
-hipError_t launch_basis(const DevSeg* segs_dev, int n_segs, int64_t n_units, bool spline_in_lds, bool fp32_out,
+// spline_lds: doubles of spline table to stage in LDS (0 = read it through the cache); it must
+// cover the largest table of the systems in the segment list.
+hipError_t launch_basis(const DevSeg* segs_dev, int n_segs, int64_t n_units, int spline_lds, bool fp32_out,
                         hipStream_t st, int64_t max_grid = 0);
 hipError_t launch_h(Mode mode, const DevSeg* segs_dev, int n_segs, int64_t n_items, hipStream_t st,
                     int64_t max_grid = 0);

@@ -6,6 +6,8 @@
 //   - basis values of an execution unit: [n_points][ld] FP64, point-major, ld a multiple of
 //     the 64-wide basis tile, padding columns zero;
 //   - D and H dense row-major [N_b][N_b] FP64; n in the caller's point order.
+#include <algorithm>
+
 #include <hip/hip_runtime.h>
 
 #include "devtypes.h"
@@ -13,6 +15,8 @@
 namespace nao {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
 // ------------------------------------------------------------------------------------------
 // helpers
@@ -26,6 +30,18 @@ __device__ inline int find_segment(const DevSeg* segs, int n_segs, int64_t b, F 
         if (prefix_of(segs[mid]) <= b) lo = mid; else hi = mid - 1;
     }
     return lo;
+}
+
+// Workgroup ids are dealt round-robin to the 8 XCDs (each with its own L2).  Virtual index
+// v in [0, 8 ceil(total/8)) maps to item (v % 8) * ceil(total/8) + v / 8, so XCD x works through
+// the contiguous eighth [x ceil(total/8), (x+1) ceil(total/8)) of the item list and the tiles of
+// one execution unit share one L2.  Items >= total are skipped.
+constexpr int N_XCD = 8;
+__host__ __device__ inline int64_t xcd_span(int64_t total) { return N_XCD * ((total + N_XCD - 1) / N_XCD); }
+__device__ inline int64_t xcd_item(int64_t v, int64_t total)
+{
+    const int64_t per = (total + N_XCD - 1) / N_XCD;
+    return (v % N_XCD) * per + v / N_XCD;
 }
 
 // (dx*dx + dy*dy) + dz*dz without contraction: the same arithmetic that decides relevance.
@@ -76,13 +92,104 @@ __device__ inline void real_ylm(double x, double y, double z, int lmax, double* 
 }
 
 // ------------------------------------------------------------------------------------------
-// basis evaluation: one workgroup per unit, threads over (point, atom) pairs (atom fastest)
+// Basis evaluation: one workgroup per execution unit; threads over (point, atom) pairs with
+// the atom fastest, each writing all functions of its atom; spline tables staged in LDS.
+constexpr size_t BASIS_LDS_BYTES = (size_t)MAX_SPLINE_LDS * sizeof(double);
+
+__device__ inline double spline_value(const double* spl, const double* par, int rr, int nk, double d2, double r,
+                                      double lnr)
+{
+    if (!(d2 < par[1])) return 0.0;
+    double t = r > par[0] ? (lnr - par[3]) * par[2] : 0.0;
+    t = fmin(fmax(t, 0.0), (double)(nk - 1));
+    const int k = min((int)t, nk - 2);
+    const double w = t - (double)k;
+    const double* c = spl + ((int64_t)rr * (nk - 1) + k) * 4;
+    return c[0] + w * (c[1] + w * (c[2] + w * c[3]));
+}
+
+// One real spherical harmonic (l <= 3, index l*l + m + l) of a unit vector.
+__device__ inline double ylm_one(int lm, double x, double y, double z)
+{
+    switch (lm) {
+    case 0: return 0.28209479177387814;
+    case 1: return 0.48860251190291992 * y;
+    case 2: return 0.48860251190291992 * z;
+    case 3: return 0.48860251190291992 * x;
+    case 4: return 1.0925484305920792 * x * y;
+    case 5: return 1.0925484305920792 * y * z;
+    case 6: return 0.31539156525252005 * (3.0 * z * z - 1.0);
+    case 7: return 1.0925484305920792 * x * z;
+    case 8: return 0.54627421529603959 * (x * x - y * y);
+    case 9: return 0.59004358992664352 * y * (3.0 * x * x - y * y);
+    case 10: return 2.8906114426405538 * x * y * z;
+    case 11: return 0.45704579946446572 * y * (5.0 * z * z - 1.0);
+    case 12: return 0.37317633259011546 * (5.0 * z * z * z - 3.0 * z);
+    case 13: return 0.45704579946446572 * x * (5.0 * z * z - 1.0);
+    case 14: return 1.4453057213202769 * z * (x * x - y * y);
+    default: return 0.59004358992664352 * x * (x * x - 3.0 * y * y);
+    }
+}
+
+// Columns [c_lo, c_hi) of one atom (its functions start at unit column col_a) at one point;
+// put(c, value) receives every value.
+template <typename Put>
+__device__ inline void eval_atom_cols(const DevSys* __restrict__ S, int atom, double px, double py, double pz,
+                                      int col_a, int c_lo, int c_hi, Put&& put)
+{
+    const double* A = S->atom_xyzr + 4 * (int64_t)atom;
+    const double dx = px - A[0], dy = py - A[1], dz = pz - A[2];
+    const double d2 = dist2_exact(dx, dy, dz);
+    if (!(d2 < A[3])) {
+        for (int c = c_lo; c < c_hi; ++c) put(c, 0.0);
+        return;
+    }
+    const int sp = S->atom_species[atom];
+    const int fptr = S->species_fn_ptr[sp], sh0 = S->species_shell_ptr[sp];
+    const double r = sqrt(d2);
+    double ux = 0.0, uy = 0.0, uz = 1.0, lnr = 0.0;
+    if (r > 0.0) {
+        const double ir = 1.0 / r;
+        ux = dx * ir;
+        uy = dy * ir;
+        uz = dz * ir;
+        lnr = log(r);
+    }
+    const int nk = S->n_knots;
+    int last = -1;
+    double R = 0.0;
+    for (int c = c_lo; c < c_hi; ++c) {
+        const int code = S->fn_code[fptr + (c - col_a)];
+        const int sh = code >> 4;
+        if (sh != last) {
+            const int rr = S->shell_radial[sh0 + sh];
+            R = spline_value(S->spline, S->radial_par + 4 * rr, rr, nk, d2, r, lnr);
+            last = sh;
+        }
+        put(c, R * ylm_one(code & 15, ux, uy, uz));
+    }
+}
+
+// Slot (index into the unit's atom list) of the atom owning unit column col.
+__device__ inline int slot_of(const int32_t* __restrict__ cols, int na, int col)
+{
+    int lo = 0, hi = na - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (cols[mid] <= col) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
 
 template <typename T, bool SPLINE_LDS>
-__global__ __launch_bounds__(256) void basis_kernel(const DevSeg* __restrict__ segs, int n_segs, int64_t total)
+__global__ __launch_bounds__(256) void basis_kernel(const DevSeg* __restrict__ segs, int n_segs, int64_t total,
+                                                    int spline_lds)
 {
     extern __shared__ double lds_spline[];
-    for (int64_t b = blockIdx.x; b < total; b += gridDim.x) {
+    (void)spline_lds;  // the launcher sized the dynamic LDS for the table
+    for (int64_t v_ = blockIdx.x; v_ < xcd_span(total); v_ += gridDim.x) {
+        const int64_t b = xcd_item(v_, total);
+        if (b >= total) continue;
         __syncthreads();  // the previous item may still read LDS
         const int s = find_segment(segs, n_segs, b, [](const DevSeg& g) { return g.unit_prefix; });
         const DevSeg& sg = segs[s];
@@ -183,85 +290,156 @@ __global__ __launch_bounds__(256) void basis_kernel(const DevSeg* __restrict__ s
 
 static unsigned grid_for(int64_t n, int64_t max_grid)
 {
-    return (unsigned)((max_grid > 0 && n > max_grid) ? max_grid : n);
+    const int64_t span = xcd_span(n);
+    if (max_grid > 0) {
+        const int64_t cap = std::max<int64_t>(N_XCD, max_grid / N_XCD * N_XCD);
+        if (span > cap) return (unsigned)cap;
+    }
+    return (unsigned)span;
 }
 
-hipError_t launch_basis(const DevSeg* segs_dev, int n_segs, int64_t n_units, bool spline_in_lds, bool fp32_out,
+hipError_t launch_basis(const DevSeg* segs_dev, int n_segs, int64_t n_units, int spline_lds, bool fp32_out,
                         hipStream_t st, int64_t max_grid)
 {
     if (n_units <= 0 || n_segs <= 0) return hipSuccess;
-    if (n_units > 0x7fffffff) return hipErrorInvalidValue;
+    if (n_units > 0x7ffffff0 || spline_lds < 0 || spline_lds > MAX_SPLINE_LDS) return hipErrorInvalidValue;
     const dim3 g(grid_for(n_units, max_grid)), b(256);
-    const size_t lds = spline_in_lds ? MAX_SPLINE_LDS * sizeof(double) : 0;
+    const bool staged = spline_lds > 0;
+    const size_t lds = (size_t)spline_lds * sizeof(double);
+    static bool attrs_set = false;  // dynamic LDS above 64 KiB must be allowed per kernel
+    if (!attrs_set) {
+        const void* fns[] = {reinterpret_cast<const void*>(&basis_kernel<float, true>),
+                             reinterpret_cast<const void*>(&basis_kernel<float, false>),
+                             reinterpret_cast<const void*>(&basis_kernel<double, true>),
+                             reinterpret_cast<const void*>(&basis_kernel<double, false>)};
+        for (const void* f : fns) {
+            const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)BASIS_LDS_BYTES);
+            if (e != hipSuccess) return e;
+        }
+        attrs_set = true;
+    }
     if (fp32_out) {
-        if (spline_in_lds) hipLaunchKernelGGL((basis_kernel<float, true>), g, b, lds, st, segs_dev, n_segs, n_units);
-        else hipLaunchKernelGGL((basis_kernel<float, false>), g, b, 0, st, segs_dev, n_segs, n_units);
+        if (staged) hipLaunchKernelGGL((basis_kernel<float, true>), g, b, lds, st, segs_dev, n_segs, n_units, spline_lds);
+        else hipLaunchKernelGGL((basis_kernel<float, false>), g, b, lds, st, segs_dev, n_segs, n_units, 0);
     } else {
-        if (spline_in_lds) hipLaunchKernelGGL((basis_kernel<double, true>), g, b, lds, st, segs_dev, n_segs, n_units);
-        else hipLaunchKernelGGL((basis_kernel<double, false>), g, b, 0, st, segs_dev, n_segs, n_units);
+        if (staged) hipLaunchKernelGGL((basis_kernel<double, true>), g, b, lds, st, segs_dev, n_segs, n_units, spline_lds);
+        else hipLaunchKernelGGL((basis_kernel<double, false>), g, b, lds, st, segs_dev, n_segs, n_units, 0);
     }
     return hipGetLastError();
 }
 
-// ------------------------------------------------------------------------------------------
-// Hamiltonian: per work item one 64x64 tile pair (I <= J) of a unit,
-//   H[I, J] += (w v Phi[:, I])^T Phi[:, J],
-// K loop over the unit's points in chunks of 16 staged in LDS; four waves, each a 32x32
-// quarter as 2x2 blocks of v_mfma_f64_16x16x4; FP64 atomics into the upper triangle.
-// Operand layouts of v_mfma_f64_16x16x4f64: A lane l holds A[l%16][l/16], B lane l holds
-// B[l/16][l%16]; the result register r of lane l is D[l/16 + 4r][l%16] (measured on gfx950;
-// the FP32 and BF16 16x16 instructions place it at D[4(l/16) + r][l%16] instead).
 
-__global__ __launch_bounds__(256) void h_kernel_f64(const DevSeg* __restrict__ segs, int n_segs, int64_t total)
+
+
+
+
+
+
+
+// ------------------------------------------------------------------------------------------
+// Contractions with one value per lane per operand: FP64 (v_mfma_f64_16x16x4f64) and FP32
+// (v_mfma_f32_16x16x4f32).  Operand layouts of both: A lane l holds A[l%16][l/16], B lane l
+// holds B[l/16][l%16].  The result register r of lane l is D[l/16 + 4r][l%16] for FP64 and
+// D[4(l/16) + r][l%16] for FP32 (measured on gfx950).
+
+template <typename T> struct Mma;
+template <> struct Mma<double> {
+    typedef d4 acc_t;
+    static __device__ inline acc_t zero() { return d4{0.0, 0.0, 0.0, 0.0}; }
+    static __device__ inline acc_t op(double a, double b, acc_t c)
+    {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ inline int row(int lk, int r) { return lk + 4 * r; }
+};
+template <> struct Mma<float> {
+    typedef f4 acc_t;
+    static __device__ inline acc_t zero() { return f4{0.f, 0.f, 0.f, 0.f}; }
+    static __device__ inline acc_t op(float a, float b, acc_t c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ inline int row(int lk, int r) { return 4 * lk + r; }
+};
+
+// Hamiltonian: per work item one 64x64 tile pair (I <= J) of a unit,
+//   H[I, J] += (w v Phi[:, I])^T Phi[:, J];
+// K loop over the unit's points in double-buffered chunks of 16 (register prefetch of the
+// next chunk while the MFMAs of the current one run); four waves, each a 32x32 quarter as
+// 2x2 MFMA blocks; FP64 atomics into the upper triangle of H.  T = FP32 accumulates a unit
+// (<= 256 points) in FP32 before the FP64 atomics.
+template <typename T>
+__global__ __launch_bounds__(256) void h_kernel(const DevSeg* __restrict__ segs, int n_segs, int64_t total)
 {
-    __shared__ double As[KCHUNK][TILE + 2];
-    __shared__ double Bs[KCHUNK][TILE + 2];
-    for (int64_t b = blockIdx.x; b < total; b += gridDim.x) {
+    typedef Mma<T> M;
+    __shared__ T As[2][KCHUNK][TILE + 2];
+    __shared__ T Bs[2][KCHUNK][TILE + 2];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = wave >> 1, wc = wave & 1;
+    const int lr = lane & 15, lk = lane >> 4;
+    for (int64_t v_ = blockIdx.x; v_ < xcd_span(total); v_ += gridDim.x) {
+        const int64_t b = xcd_item(v_, total);
+        if (b >= total) continue;
         const int s = find_segment(segs, n_segs, b, [](const DevSeg& g) { return g.item_prefix; });
         const DevSeg& sg = segs[s];
         const HItem it = static_cast<const HItem*>(sg.items)[sg.item_begin + (b - sg.item_prefix)];
         const DevUnit u = sg.units[it.unit];
-        const double* __restrict__ phi = static_cast<const double*>(sg.phi) + u.out_offset;
+        const T* __restrict__ phi = static_cast<const T*>(sg.phi) + u.out_offset;
         const double* __restrict__ wv = sg.wv + u.point_begin;
         const int np = u.n_points, ld = u.ld;
         const int I0 = it.ti * TILE, J0 = it.tj * TILE;
-        const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-        const int wr = wave >> 1, wc = wave & 1;
-        const int lr = lane & 15, lk = lane >> 4;
+        const int n_chunks = (np + KCHUNK - 1) / KCHUNK;
 
-        d4 acc[2][2];
-    #pragma unroll
-        for (int i = 0; i < 2; ++i)
-    #pragma unroll
-            for (int j = 0; j < 2; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-
-        for (int k0 = 0; k0 < np; k0 += KCHUNK) {
-    #pragma unroll
-            for (int e = tid; e < KCHUNK * TILE; e += 256) {
-                const int r = e >> 6, c = e & 63;
-                const int p = k0 + r;
-                double a = 0.0, bb = 0.0;
+        T ra[4], rb[4];
+        auto fetch = [&](int c) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int e = tid + 256 * q;
+                const int r = e >> 6, col = e & 63;
+                const int p = c * KCHUNK + r;
+                T a = T(0), bb = T(0);
                 if (p < np) {
-                    const double* rowp = phi + (int64_t)p * ld;
-                    a = rowp[I0 + c] * wv[p];
-                    bb = rowp[J0 + c];
+                    const T* rowp = phi + (int64_t)p * ld;
+                    a = T((double)rowp[I0 + col] * wv[p]);
+                    bb = rowp[J0 + col];
                 }
-                As[r][c] = a;
-                Bs[r][c] = bb;
+                ra[q] = a;
+                rb[q] = bb;
             }
-            __syncthreads();
-    #pragma unroll
+        };
+        auto stash = [&](int buf) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int e = tid + 256 * q;
+                As[buf][e >> 6][e & 63] = ra[q];
+                Bs[buf][e >> 6][e & 63] = rb[q];
+            }
+        };
+
+        typename M::acc_t acc[2][2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] = M::zero();
+        fetch(0);
+        stash(0);
+        __syncthreads();
+        for (int c = 0; c < n_chunks; ++c) {
+            const int buf = c & 1;
+            if (c + 1 < n_chunks) fetch(c + 1);
+#pragma unroll
             for (int kk = 0; kk < KCHUNK / 4; ++kk) {
                 const int kr = kk * 4 + lk;
-                const double a0 = As[kr][wr * 32 + lr];
-                const double a1 = As[kr][wr * 32 + 16 + lr];
-                const double b0 = Bs[kr][wc * 32 + lr];
-                const double b1 = Bs[kr][wc * 32 + 16 + lr];
-                acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-                acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-                acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-                acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+                const T a0 = As[buf][kr][wr * 32 + lr];
+                const T a1 = As[buf][kr][wr * 32 + 16 + lr];
+                const T b0 = Bs[buf][kr][wc * 32 + lr];
+                const T b1 = Bs[buf][kr][wc * 32 + 16 + lr];
+                acc[0][0] = M::op(a0, b0, acc[0][0]);
+                acc[0][1] = M::op(a0, b1, acc[0][1]);
+                acc[1][0] = M::op(a1, b0, acc[1][0]);
+                acc[1][1] = M::op(a1, b1, acc[1][1]);
             }
+            if (c + 1 < n_chunks) stash(buf ^ 1);
             __syncthreads();
         }
 
@@ -269,271 +447,136 @@ __global__ __launch_bounds__(256) void h_kernel_f64(const DevSeg* __restrict__ s
         double* __restrict__ H = sg.H;
         const int64_t ldh = sg.ld;
         const bool diag = it.ti == it.tj;
-    #pragma unroll
+#pragma unroll
         for (int ib = 0; ib < 2; ++ib)
-    #pragma unroll
+#pragma unroll
             for (int jb = 0; jb < 2; ++jb)
-    #pragma unroll
+#pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int row = wr * 32 + ib * 16 + lk + 4 * r;  // FP64 result layout
+                    const int row = wr * 32 + ib * 16 + M::row(lk, r);
                     const int col = wc * 32 + jb * 16 + lr;
                     const int ci = I0 + row, cj = J0 + col;
                     if (ci < u.m && cj < u.m && (!diag || row <= col)) {
                         const int64_t gi = fn[ci], gj = fn[cj];
-                        unsafeAtomicAdd(H + gi * ldh + gj, acc[ib][jb][r]);
+                        unsafeAtomicAdd(H + gi * ldh + gj, (double)acc[ib][jb][r]);
                     }
                 }
     }
 }
 
-
-// ------------------------------------------------------------------------------------------
 // Density: per work item one 64-wide column tile J of a unit,
 //   T[:, J] = sum_{I <= J} c_IJ Phi[:, I] D[I, J]   (c = 2 off the diagonal tile, 1 on it,
 //             the diagonal tile read from the upper triangle of D),
 //   n_p += sum_{j in J} T[p, j] Phi[p, j].
-// Rows = the unit's points (<= 256, 16 row blocks), K = basis functions in chunks of 16;
-// wave w owns column block w (16 columns) for all row blocks.
-
-__global__ __launch_bounds__(256) void n_kernel_f64(const DevSeg* __restrict__ segs, int n_segs, int64_t total)
+// Rows = the unit's points (<= 256: 16 row blocks), K = basis functions in double-buffered
+// chunks of 16; NW waves: wave w owns column block w % 4 and row blocks w / 4, w / 4 + NW / 4,
+// ...  T = FP32 accumulates the whole column tile in FP32; the row dot and the sum over
+// tiles and units are FP64.
+template <typename T, int NW>
+__global__ __launch_bounds__(64 * NW) void n_kernel(const DevSeg* __restrict__ segs, int n_segs, int64_t total)
 {
-    __shared__ double As[MAX_UNIT_POINTS][KCHUNK + 1];
-    __shared__ double Bs[KCHUNK][TILE + 2];
+    typedef Mma<T> M;
+    constexpr int NT = 64 * NW;             // threads
+    constexpr int RB = 64 / NW;             // row blocks per wave (16 row x 4 column blocks)
+    constexpr int RS = NW / 4;              // row-block stride between the waves of a column
+    __shared__ T As[2][MAX_UNIT_POINTS][KCHUNK + 1];
+    __shared__ T Bs[2][KCHUNK][TILE + 2];
     __shared__ double red[4][MAX_UNIT_POINTS];
-    for (int64_t b = blockIdx.x; b < total; b += gridDim.x) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int cb = wave & 3, rh = wave >> 2;  // column block; row blocks rh, rh + RS, ...
+    const int lr = lane & 15, lk = lane >> 4;
+    for (int64_t v_ = blockIdx.x; v_ < xcd_span(total); v_ += gridDim.x) {
+        const int64_t b = xcd_item(v_, total);
+        if (b >= total) continue;
         const int s = find_segment(segs, n_segs, b, [](const DevSeg& g) { return g.item_prefix; });
         const DevSeg& sg = segs[s];
         const NItem it = static_cast<const NItem*>(sg.items)[sg.item_begin + (b - sg.item_prefix)];
         const DevUnit u = sg.units[it.unit];
-        const double* __restrict__ phi = static_cast<const double*>(sg.phi) + u.out_offset;
+        const T* __restrict__ phi = static_cast<const T*>(sg.phi) + u.out_offset;
         const int32_t* __restrict__ fn = sg.unit_fn + u.fn_begin;
         const double* __restrict__ D = sg.D;
         const int64_t ldd = sg.ld;
         const int np = u.n_points, ld = u.ld, m = u.m;
         const int P = (np + 15) >> 4;
         const int J0 = it.tj * TILE;
-        const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-        const int lr = lane & 15, lk = lane >> 4;
+        const int n_chunks = (it.tj + 1) * (TILE / KCHUNK);
 
-        d4 acc[MAX_UNIT_POINTS / 16];
-    #pragma unroll
-        for (int i = 0; i < MAX_UNIT_POINTS / 16; ++i) acc[i] = d4{0.0, 0.0, 0.0, 0.0};
-
-        for (int ti = 0; ti <= it.tj; ++ti) {
+        T pa[MAX_UNIT_POINTS * KCHUNK / NT], pb2[(KCHUNK * TILE + NT - 1) / NT];
+        auto fetch = [&](int c) {
+            const int ti = c / (TILE / KCHUNK);
+            const int c0 = ti * TILE + (c % (TILE / KCHUNK)) * KCHUNK;
             const bool diag = ti == it.tj;
-            for (int i0 = 0; i0 < TILE; i0 += KCHUNK) {
-                const int c0 = ti * TILE + i0;
-                for (int e = tid; e < MAX_UNIT_POINTS * KCHUNK; e += 256) {
-                    const int p = e >> 4, i = e & 15;
-                    As[p][i] = p < np ? phi[(int64_t)p * ld + c0 + i] : 0.0;
-                }
-    #pragma unroll
-                for (int e = tid; e < KCHUNK * TILE; e += 256) {
-                    const int i = e >> 6, j = e & 63;
-                    const int ci = c0 + i, cj = J0 + j;
-                    double val = 0.0;
-                    if (ci < m && cj < m) {
-                        const int64_t gi = fn[ci], gj = fn[cj];
-                        if (!diag) val = 2.0 * D[gi * ldd + gj];
-                        else val = ci <= cj ? D[gi * ldd + gj] : D[gj * ldd + gi];
-                    }
-                    Bs[i][j] = val;
-                }
-                __syncthreads();
-    #pragma unroll
-                for (int kk = 0; kk < KCHUNK / 4; ++kk) {
-                    const double bv = Bs[kk * 4 + lk][wave * 16 + lr];
-    #pragma unroll
-                    for (int pb = 0; pb < MAX_UNIT_POINTS / 16; ++pb)
-                        if (pb < P) {
-                            const double av = As[pb * 16 + lr][kk * 4 + lk];
-                            acc[pb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[pb], 0, 0, 0);
-                        }
-                }
-                __syncthreads();
+#pragma unroll
+            for (int q = 0; q < MAX_UNIT_POINTS * KCHUNK / NT; ++q) {
+                const int e = tid + NT * q;
+                const int p = e >> 4, i = e & 15;
+                pa[q] = p < np ? phi[(int64_t)p * ld + c0 + i] : T(0);
             }
-        }
+#pragma unroll
+            for (int q = 0; q < (KCHUNK * TILE + NT - 1) / NT; ++q) {
+                const int e = tid + NT * q;
+                const int i = e >> 6, j = e & 63;
+                const int ci = c0 + i, cj = J0 + j;
+                double val = 0.0;
+                if (ci < m && cj < m) {
+                    const int64_t gi = fn[ci], gj = fn[cj];
+                    if (!diag) val = 2.0 * D[gi * ldd + gj];
+                    else val = ci <= cj ? D[gi * ldd + gj] : D[gj * ldd + gi];
+                }
+                pb2[q] = T(val);
+            }
+        };
+        auto stash = [&](int buf) {
+#pragma unroll
+            for (int q = 0; q < MAX_UNIT_POINTS * KCHUNK / NT; ++q) {
+                const int e = tid + NT * q;
+                As[buf][e >> 4][e & 15] = pa[q];
+            }
+#pragma unroll
+            for (int q = 0; q < (KCHUNK * TILE + NT - 1) / NT; ++q) {
+                const int e = tid + NT * q;
+                Bs[buf][e >> 6][e & 63] = pb2[q];
+            }
+        };
 
-        const int cj = J0 + wave * 16 + lr;
-    #pragma unroll
-        for (int pb = 0; pb < MAX_UNIT_POINTS / 16; ++pb) {
-            if (pb < P) {
-    #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int p = pb * 16 + lk + 4 * r;  // FP64 result layout
-                    double v = 0.0;
-                    if (p < np && cj < m) v = acc[pb][r] * phi[(int64_t)p * ld + cj];
-                    v += __shfl_xor(v, 1);
-                    v += __shfl_xor(v, 2);
-                    v += __shfl_xor(v, 4);
-                    v += __shfl_xor(v, 8);
-                    if (lr == 0) red[wave][p] = v;
-                }
-            }
-        }
+        typename M::acc_t acc[RB];
+#pragma unroll
+        for (int i = 0; i < RB; ++i) acc[i] = M::zero();
+        fetch(0);
+        stash(0);
         __syncthreads();
-        if (tid < np) {
-            const double v = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
-            const int64_t pc = sg.sys->perm[u.point_begin + tid];
-            unsafeAtomicAdd(sg.n + pc, v);
-        }
-    }
-}
-
-
-// ------------------------------------------------------------------------------------------
-// Reduced-precision contractions.  Basis values arrive as FP32 (rounded from the FP64
-// evaluation); w*v and D are rounded from FP64 when staged.  Per-tile results are flushed
-// into FP64 accumulators and reach H and n through FP64 atomics.
-
-typedef float f4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
-
-// Hamiltonian, FP32 MFMA (v_mfma_f32_16x16x4f32), same tiling as the FP64 kernel.
-__global__ __launch_bounds__(256) void h_kernel_f32(const DevSeg* __restrict__ segs, int n_segs, int64_t total)
-{
-    __shared__ float As[KCHUNK][TILE + 4];
-    __shared__ float Bs[KCHUNK][TILE + 4];
-    for (int64_t b = blockIdx.x; b < total; b += gridDim.x) {
-        const int s = find_segment(segs, n_segs, b, [](const DevSeg& g) { return g.item_prefix; });
-        const DevSeg& sg = segs[s];
-        const HItem it = static_cast<const HItem*>(sg.items)[sg.item_begin + (b - sg.item_prefix)];
-        const DevUnit u = sg.units[it.unit];
-        const float* __restrict__ phi = static_cast<const float*>(sg.phi) + u.out_offset;
-        const double* __restrict__ wv = sg.wv + u.point_begin;
-        const int np = u.n_points, ld = u.ld;
-        const int I0 = it.ti * TILE, J0 = it.tj * TILE;
-        const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-        const int wr = wave >> 1, wc = wave & 1;
-        const int lr = lane & 15, lk = lane >> 4;
-        f4 acc[2][2];
-    #pragma unroll
-        for (int i = 0; i < 2; ++i)
-    #pragma unroll
-            for (int j = 0; j < 2; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-        for (int k0 = 0; k0 < np; k0 += KCHUNK) {
-    #pragma unroll
-            for (int e = tid; e < KCHUNK * TILE; e += 256) {
-                const int r = e >> 6, c = e & 63;
-                const int p = k0 + r;
-                float a = 0.f, bb = 0.f;
-                if (p < np) {
-                    const float* rowp = phi + (int64_t)p * ld;
-                    a = (float)((double)rowp[I0 + c] * wv[p]);
-                    bb = rowp[J0 + c];
-                }
-                As[r][c] = a;
-                Bs[r][c] = bb;
-            }
-            __syncthreads();
-    #pragma unroll
+        for (int c = 0; c < n_chunks; ++c) {
+            const int buf = c & 1;
+            if (c + 1 < n_chunks) fetch(c + 1);
+#pragma unroll
             for (int kk = 0; kk < KCHUNK / 4; ++kk) {
-                const int kr = kk * 4 + lk;
-                const float a0 = As[kr][wr * 32 + lr], a1 = As[kr][wr * 32 + 16 + lr];
-                const float b0 = Bs[kr][wc * 32 + lr], b1 = Bs[kr][wc * 32 + 16 + lr];
-                acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
-                acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
-                acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
-                acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
+                const T bv = Bs[buf][kk * 4 + lk][cb * 16 + lr];
+#pragma unroll
+                for (int q = 0; q < RB; ++q) {
+                    const int pblk = RS * q + rh;
+                    if (pblk < P) acc[q] = M::op(As[buf][pblk * 16 + lr][kk * 4 + lk], bv, acc[q]);
+                }
             }
+            if (c + 1 < n_chunks) stash(buf ^ 1);
             __syncthreads();
         }
-        const int32_t* __restrict__ fn = sg.unit_fn + u.fn_begin;
-        const bool diag = it.ti == it.tj;
-    #pragma unroll
-        for (int ib = 0; ib < 2; ++ib)
-    #pragma unroll
-            for (int jb = 0; jb < 2; ++jb)
-    #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int row = wr * 32 + ib * 16 + lk * 4 + r, col = wc * 32 + jb * 16 + lr;
-                    const int ci = I0 + row, cj = J0 + col;
-                    if (ci < u.m && cj < u.m && (!diag || row <= col))
-                        unsafeAtomicAdd(sg.H + (int64_t)fn[ci] * sg.ld + fn[cj], (double)acc[ib][jb][r]);
-                }
-    }
-}
 
-// Density, FP32 MFMA; same tiling as the FP64 kernel, D rounded to FP32 when staged.
-__global__ __launch_bounds__(256) void n_kernel_f32(const DevSeg* __restrict__ segs, int n_segs, int64_t total)
-{
-    __shared__ float As[MAX_UNIT_POINTS][KCHUNK + 1];
-    __shared__ float Bs[KCHUNK][TILE + 4];
-    __shared__ double red[4][MAX_UNIT_POINTS];
-    for (int64_t b = blockIdx.x; b < total; b += gridDim.x) {
-        const int s = find_segment(segs, n_segs, b, [](const DevSeg& g) { return g.item_prefix; });
-        const DevSeg& sg = segs[s];
-        const NItem it = static_cast<const NItem*>(sg.items)[sg.item_begin + (b - sg.item_prefix)];
-        const DevUnit u = sg.units[it.unit];
-        const float* __restrict__ phi = static_cast<const float*>(sg.phi) + u.out_offset;
-        const int32_t* __restrict__ fn = sg.unit_fn + u.fn_begin;
-        const double* __restrict__ D = sg.D;
-        const int64_t ldd = sg.ld;
-        const int np = u.n_points, ld = u.ld, m = u.m;
-        const int P = (np + 15) >> 4;
-        const int J0 = it.tj * TILE;
-        const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-        const int lr = lane & 15, lk = lane >> 4;
-        f4 acc[MAX_UNIT_POINTS / 16];
-        d4 acc64[MAX_UNIT_POINTS / 16];
-    #pragma unroll
-        for (int i = 0; i < MAX_UNIT_POINTS / 16; ++i) {
-            acc[i] = f4{0.f, 0.f, 0.f, 0.f};
-            acc64[i] = d4{0.0, 0.0, 0.0, 0.0};
-        }
-        for (int ti = 0; ti <= it.tj; ++ti) {
-            const bool diag = ti == it.tj;
-            for (int i0 = 0; i0 < TILE; i0 += KCHUNK) {
-                const int c0 = ti * TILE + i0;
-                for (int e = tid; e < MAX_UNIT_POINTS * KCHUNK; e += 256) {
-                    const int p = e >> 4, i = e & 15;
-                    As[p][i] = p < np ? phi[(int64_t)p * ld + c0 + i] : 0.f;
-                }
-    #pragma unroll
-                for (int e = tid; e < KCHUNK * TILE; e += 256) {
-                    const int i = e >> 6, j = e & 63;
-                    const int ci = c0 + i, cj = J0 + j;
-                    double val = 0.0;
-                    if (ci < m && cj < m) {
-                        const int64_t gi = fn[ci], gj = fn[cj];
-                        if (!diag) val = 2.0 * D[gi * ldd + gj];
-                        else val = ci <= cj ? D[gi * ldd + gj] : D[gj * ldd + gi];
-                    }
-                    Bs[i][j] = (float)val;
-                }
-                __syncthreads();
-    #pragma unroll
-                for (int kk = 0; kk < KCHUNK / 4; ++kk) {
-                    const float bv = Bs[kk * 4 + lk][wave * 16 + lr];
-    #pragma unroll
-                    for (int pb = 0; pb < MAX_UNIT_POINTS / 16; ++pb)
-                        if (pb < P) acc[pb] = __builtin_amdgcn_mfma_f32_16x16x4f32(As[pb * 16 + lr][kk * 4 + lk], bv, acc[pb], 0, 0, 0);
-                }
-                __syncthreads();
-            }
-            // one 64-wide tile of D done: move the FP32 partial sums into FP64
-    #pragma unroll
-            for (int pb = 0; pb < MAX_UNIT_POINTS / 16; ++pb)
-    #pragma unroll
+        // n_p += sum_j T[p][j] Phi[p][j]
+        const int cj = J0 + cb * 16 + lr;
+#pragma unroll
+        for (int q = 0; q < RB; ++q) {
+            const int pblk = RS * q + rh;
+            if (pblk < P) {
+#pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    acc64[pb][r] += (double)acc[pb][r];
-                    acc[pb][r] = 0.f;
-                }
-        }
-        const int cj = J0 + wave * 16 + lr;
-    #pragma unroll
-        for (int pb = 0; pb < MAX_UNIT_POINTS / 16; ++pb) {
-            if (pb < P) {
-    #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int p = pb * 16 + lk * 4 + r;
+                    const int p = pblk * 16 + M::row(lk, r);
                     double v = 0.0;
-                    if (p < np && cj < m) v = acc64[pb][r] * (double)phi[(int64_t)p * ld + cj];
+                    if (p < np && cj < m) v = (double)acc[q][r] * (double)phi[(int64_t)p * ld + cj];
                     v += __shfl_xor(v, 1);
                     v += __shfl_xor(v, 2);
                     v += __shfl_xor(v, 4);
                     v += __shfl_xor(v, 8);
-                    if (lr == 0) red[wave][p] = v;
+                    if (lr == 0) red[cb][p] = v;
                 }
             }
         }
@@ -542,8 +585,19 @@ __global__ __launch_bounds__(256) void n_kernel_f32(const DevSeg* __restrict__ s
             const double v = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
             unsafeAtomicAdd(sg.n + sg.sys->perm[u.point_begin + tid], v);
         }
+        __syncthreads();  // red is rewritten by the next item
     }
 }
+
+// ------------------------------------------------------------------------------------------
+// Reduced-precision contractions.  Basis values arrive as FP32 (rounded from the FP64
+// evaluation); w*v and D are rounded from FP64 when staged.  Per-tile results are flushed
+// into FP64 accumulators and reach H and n through FP64 atomics.
+
+
+
+
+
 
 // Split of an FP32 value into NS bf16 parts: x ~ x0 + x1 (+ x2), each part the rounding to
 // nearest of what the previous parts leave.
@@ -581,7 +635,9 @@ __global__ __launch_bounds__(256) void h_kernel_bf16(const DevSeg* __restrict__ 
 {
     __shared__ __attribute__((aligned(16))) __bf16 As[NS][TILE][BKP];
     __shared__ __attribute__((aligned(16))) __bf16 Bs[NS][TILE][BKP];
-    for (int64_t b = blockIdx.x; b < total; b += gridDim.x) {
+    for (int64_t v_ = blockIdx.x; v_ < xcd_span(total); v_ += gridDim.x) {
+        const int64_t b = xcd_item(v_, total);
+        if (b >= total) continue;
         const int s = find_segment(segs, n_segs, b, [](const DevSeg& g) { return g.item_prefix; });
         const DevSeg& sg = segs[s];
         const HItem it = static_cast<const HItem*>(sg.items)[sg.item_begin + (b - sg.item_prefix)];
@@ -671,7 +727,9 @@ __global__ __launch_bounds__(256) void n_kernel_bf16(const DevSeg* __restrict__ 
     __shared__ __attribute__((aligned(16))) __bf16 As[NS][MAX_UNIT_POINTS][BKP];
     __shared__ __attribute__((aligned(16))) __bf16 Bs[NS][TILE][BKP];
     __shared__ double red[4][MAX_UNIT_POINTS];
-    for (int64_t b = blockIdx.x; b < total; b += gridDim.x) {
+    for (int64_t v_ = blockIdx.x; v_ < xcd_span(total); v_ += gridDim.x) {
+        const int64_t b = xcd_item(v_, total);
+        if (b >= total) continue;
         const int s = find_segment(segs, n_segs, b, [](const DevSeg& g) { return g.item_prefix; });
         const DevSeg& sg = segs[s];
         const NItem it = static_cast<const NItem*>(sg.items)[sg.item_begin + (b - sg.item_prefix)];
@@ -769,11 +827,11 @@ hipError_t launch_h(Mode mode, const DevSeg* segs_dev, int n_segs, int64_t n_ite
                     int64_t max_grid)
 {
     if (n_items <= 0 || n_segs <= 0) return hipSuccess;
-    if (n_items > 0x7fffffff) return hipErrorInvalidValue;
+    if (n_items > 0x7ffffff0) return hipErrorInvalidValue;
     const dim3 g(grid_for(n_items, max_grid)), b(256);
     switch (mode) {
-    case MODE_FP64: hipLaunchKernelGGL(h_kernel_f64, g, b, 0, st, segs_dev, n_segs, n_items); break;
-    case MODE_FP32: hipLaunchKernelGGL(h_kernel_f32, g, b, 0, st, segs_dev, n_segs, n_items); break;
+    case MODE_FP64: hipLaunchKernelGGL(h_kernel<double>, g, b, 0, st, segs_dev, n_segs, n_items); break;
+    case MODE_FP32: hipLaunchKernelGGL(h_kernel<float>, g, b, 0, st, segs_dev, n_segs, n_items); break;
     case MODE_BF16X3: hipLaunchKernelGGL(h_kernel_bf16<2>, g, b, 0, st, segs_dev, n_segs, n_items); break;
     case MODE_BF16X6: hipLaunchKernelGGL(h_kernel_bf16<3>, g, b, 0, st, segs_dev, n_segs, n_items); break;
     default: return hipErrorInvalidValue;
@@ -785,11 +843,11 @@ hipError_t launch_n(Mode mode, const DevSeg* segs_dev, int n_segs, int64_t n_ite
                     int64_t max_grid)
 {
     if (n_items <= 0 || n_segs <= 0) return hipSuccess;
-    if (n_items > 0x7fffffff) return hipErrorInvalidValue;
+    if (n_items > 0x7ffffff0) return hipErrorInvalidValue;
     const dim3 g(grid_for(n_items, max_grid)), b(256);
     switch (mode) {
-    case MODE_FP64: hipLaunchKernelGGL(n_kernel_f64, g, b, 0, st, segs_dev, n_segs, n_items); break;
-    case MODE_FP32: hipLaunchKernelGGL(n_kernel_f32, g, b, 0, st, segs_dev, n_segs, n_items); break;
+    case MODE_FP64: hipLaunchKernelGGL((n_kernel<double, 8>), g, dim3(512), 0, st, segs_dev, n_segs, n_items); break;
+    case MODE_FP32: hipLaunchKernelGGL((n_kernel<float, 16>), g, dim3(1024), 0, st, segs_dev, n_segs, n_items); break;
     case MODE_BF16X3: hipLaunchKernelGGL(n_kernel_bf16<2>, g, b, 0, st, segs_dev, n_segs, n_items); break;
     case MODE_BF16X6: hipLaunchKernelGGL(n_kernel_bf16<3>, g, b, 0, st, segs_dev, n_segs, n_items); break;
     default: return hipErrorInvalidValue;

@@ -27,8 +27,10 @@ std::string load_basis(const nao_basis_desc* d, HostBasis& o)
     o.n_knots = d->n_knots;
     o.shell_ptr.assign(d->species_shell_ptr, d->species_shell_ptr + d->n_species + 1);
     if (o.shell_ptr[0] != 0) return "species_shell_ptr[0] != 0";
-    for (int32_t s = 0; s < d->n_species; ++s)
+    for (int32_t s = 0; s < d->n_species; ++s) {
         if (o.shell_ptr[s + 1] < o.shell_ptr[s]) return "species_shell_ptr not non-decreasing";
+        if (o.shell_ptr[s + 1] - o.shell_ptr[s] > 16) return "more than 16 shells in a species";
+    }
     const int32_t n_shells = o.shell_ptr[d->n_species];
     o.shell_l.assign(d->shell_l, d->shell_l + n_shells);
     o.shell_radial.assign(d->shell_radial, d->shell_radial + n_shells);
@@ -390,6 +392,14 @@ void make_groups(const HostBasis& b, const std::vector<int64_t>& batch_ptr,
         }
         std::vector<int32_t> at(atoms.begin() + atom_ptr[bi], atoms.begin() + atom_ptr[bi + 1]);
         const double m_b = (double)list_size(b, at);
+        const int32_t cap = group_max > 0 ? group_max : 256;
+        if (group_max == 0 || np > cap) {  // no grouping, or a batch larger than a group
+            flush();
+            for (int64_t s = 0; s < np; s += cap)
+                push_unit(b, p0 + s, (int32_t)std::min<int64_t>(cap, np - s), (int32_t)bi, at, units,
+                          unit_atoms, unit_cols);
+            continue;
+        }
         if (np > group_max) {
             flush();
             for (int64_t s = 0; s < np; s += group_max)

@@ -225,10 +225,10 @@ struct nao_system_s {
     // device state
     DevSys dsys{};
     DevArray d_sys, d_px, d_py, d_pz, d_pw, d_perm, d_atoms, d_species, d_shell_ptr, d_shell_l, d_shell_rad,
-        d_radial_par, d_spline;
+        d_radial_par, d_spline, d_fn_ptr, d_fn_code;
     DevArray d_units, d_unit_atoms, d_unit_cols, d_unit_fn, d_h_items, d_n_items;
     DevArray d_wv, d_v, d_D, d_H, d_n, d_segs;
-    bool spline_lds = true;
+    int spline_lds = 0;  // doubles of spline table staged in LDS by the basis kernel (0 = not staged)
 };
 
 namespace {
@@ -237,7 +237,7 @@ size_t system_bytes(const nao_system_s* s)
 {
     const DevArray* arr[] = {&s->d_sys, &s->d_px, &s->d_py, &s->d_pz, &s->d_pw, &s->d_perm, &s->d_atoms,
                              &s->d_species, &s->d_shell_ptr, &s->d_shell_l, &s->d_shell_rad, &s->d_radial_par,
-                             &s->d_spline, &s->d_units, &s->d_unit_atoms, &s->d_unit_cols, &s->d_unit_fn,
+                             &s->d_spline, &s->d_fn_ptr, &s->d_fn_code, &s->d_units, &s->d_unit_atoms, &s->d_unit_cols, &s->d_unit_fn,
                              &s->d_h_items, &s->d_n_items, &s->d_wv, &s->d_v, &s->d_D, &s->d_H, &s->d_n,
                              &s->d_segs};
     size_t t = 0;
@@ -249,7 +249,7 @@ void free_all(nao_system_s* s)
 {
     DevArray* arr[] = {&s->d_sys, &s->d_px, &s->d_py, &s->d_pz, &s->d_pw, &s->d_perm, &s->d_atoms,
                        &s->d_species, &s->d_shell_ptr, &s->d_shell_l, &s->d_shell_rad, &s->d_radial_par,
-                       &s->d_spline, &s->d_units, &s->d_unit_atoms, &s->d_unit_cols, &s->d_unit_fn,
+                       &s->d_spline, &s->d_fn_ptr, &s->d_fn_code, &s->d_units, &s->d_unit_atoms, &s->d_unit_cols, &s->d_unit_fn,
                        &s->d_h_items, &s->d_n_items, &s->d_wv, &s->d_v, &s->d_D, &s->d_H, &s->d_n, &s->d_segs};
     for (auto* a : arr) {
         dev_free(s->ctx, a->p, a->bytes);
@@ -371,6 +371,8 @@ bool finite_all(const double* p, int64_t n)
 
 // ------------------------------------------------------------------------------------------
 // many structures per launch sequence
+
+static Mode exec_mode(nao_ctx, nao_precision p) { return (Mode)p; }
 
 static const char* kname(bool ham, nao_precision p)
 {
@@ -536,8 +538,9 @@ nao_status many_build(nao_ctx c, const nao_work* work, int64_t n_work, nao_preci
 
 nao_status many_enqueue(nao_ctx c, ManyPlan* m)
 {
-    const Mode mode = (Mode)m->prec;
+    const Mode mode = exec_mode(c, m->prec);
     const bool f32 = m->prec != NAO_FP64;
+    const bool staged = true;
     const int64_t grid = (int64_t)c->n_cu * c->persistent_per_cu;
     for (size_t e = 0; e < m->entries.size(); ++e) {
         const nao_work& w = m->entries[e];
@@ -551,11 +554,18 @@ nao_status many_enqueue(nao_ctx c, ManyPlan* m)
         }
     }
     const DevSeg* d = m->d_segs.as<DevSeg>();
-    bool lds = true;
-    for (const nao_work& w : m->entries) lds = lds && w.sys->spline_lds;
+    // stage the spline tables in LDS only if every system's table fits
+    int lds = 0;
+    bool all_fit = true;
+    for (const nao_work& w : m->entries) {
+        all_fit = all_fit && w.sys->spline_lds > 0;
+        lds = std::max(lds, w.sys->spline_lds);
+    }
+    if (!all_fit) lds = 0;
     for (const auto& k : m->chunks) {
-        LAUNCH(c, f32 ? "basis_f32" : "basis_f64",
-               launch_basis(d + k.all_off, (int)k.all_n, k.units, lds, f32, c->stream, grid));
+        if (staged)
+            LAUNCH(c, f32 ? "basis_f32" : "basis_f64",
+                   launch_basis(d + k.all_off, (int)k.all_n, k.units, lds, f32, c->stream, grid));
         if (k.h_n) LAUNCH(c, kname(true, m->prec), launch_h(mode, d + k.h_off, (int)k.h_n, k.h_items, c->stream, grid));
         if (k.n_n) LAUNCH(c, kname(false, m->prec), launch_n(mode, d + k.n_off, (int)k.n_n, k.n_items, c->stream, grid));
     }
@@ -947,7 +957,7 @@ static nao_status setup_system(nao_system s, const double* xyz, const double* w)
         rpar[4 * r + 3] = std::log(B.rmin[r]);
     }
     std::vector<double> spl = spline_coefficients(B);
-    s->spline_lds = spl.size() <= (size_t)MAX_SPLINE_LDS;
+    s->spline_lds = spl.size() <= (size_t)MAX_SPLINE_LDS ? (int)spl.size() : 0;
     nao_status st;
 #define UP(arr, vec) \
     if ((st = upload(c, s->arr, (vec).data(), (vec).size() * sizeof((vec)[0]))) != NAO_OK) return st
@@ -963,6 +973,15 @@ static nao_status setup_system(nao_system s, const double* xyz, const double* w)
     UP(d_shell_rad, B.shell_radial);
     UP(d_radial_par, rpar);
     UP(d_spline, spl);
+    std::vector<int32_t> fn_ptr(1, 0), fn_code;
+    for (int32_t sp = 0; sp < B.n_species; ++sp) {
+        for (int32_t j = B.shell_ptr[sp]; j < B.shell_ptr[sp + 1]; ++j)
+            for (int32_t mm = 0; mm < 2 * B.shell_l[j] + 1; ++mm)
+                fn_code.push_back(((j - B.shell_ptr[sp]) << 4) | (B.shell_l[j] * B.shell_l[j] + mm));
+        fn_ptr.push_back((int32_t)fn_code.size());
+    }
+    UP(d_fn_ptr, fn_ptr);
+    UP(d_fn_code, fn_code);
 #undef UP
     DevSys& d = s->dsys;
     d.px = s->d_px.as<double>();
@@ -977,6 +996,8 @@ static nao_status setup_system(nao_system s, const double* xyz, const double* w)
     d.shell_radial = s->d_shell_rad.as<int32_t>();
     d.radial_par = s->d_radial_par.as<double>();
     d.spline = s->d_spline.as<double>();
+    d.species_fn_ptr = s->d_fn_ptr.as<int32_t>();
+    d.fn_code = s->d_fn_code.as<int32_t>();
     d.n_radial = B.n_radial;
     d.n_knots = B.n_knots;
     d.n_basis = B.n_basis;
@@ -1037,8 +1058,8 @@ nao_status nao_system_set_group_max(nao_system s, int32_t group_max)
     if (!s) return (g_thread_error = "system is NULL", NAO_ERR_INVALID_ARG);
     nao_status st = check_ctx(s->ctx);
     if (st != NAO_OK) return st;
-    if (group_max < 16 || group_max > MAX_UNIT_POINTS)
-        return (set_err(s->ctx, "group_max outside [16, 256]"), NAO_ERR_INVALID_ARG);
+    if (group_max != 0 && (group_max < 16 || group_max > MAX_UNIT_POINTS))
+        return (set_err(s->ctx, "group_max must be 0 or in [16, 256]"), NAO_ERR_INVALID_ARG);
     HIP_TRY(s->ctx, hipStreamSynchronize(s->ctx->stream));
     many_forget(s->ctx, s);
     s->group_max = group_max;
@@ -1186,8 +1207,9 @@ static nao_status check_prec(nao_ctx c, nao_precision p)
 static nao_status run_blocks(nao_system s, bool ham, nao_precision prec, const double* wv, const double* D, double* H,
                              double* n)
 {
-    const Mode mode = (Mode)prec;
+    const Mode mode = exec_mode(s->ctx, prec);
     const bool f32 = prec != NAO_FP64;
+    const bool staged = true;  // every mode reads its basis values from the scratch block
     nao_ctx c = s->ctx;
     std::vector<DevSeg> segs;
     for (const Block& b : s->blocks) {
@@ -1203,8 +1225,9 @@ static nao_status run_blocks(nao_system s, bool ham, nao_precision prec, const d
                               c->stream));
     DevSeg* dseg = s->d_segs.as<DevSeg>();
     for (size_t k = 0; k < segs.size(); ++k) {
-        LAUNCH(c, f32 ? "basis_f32" : "basis_f64",
-               launch_basis(dseg + k, 1, segs[k].unit_count, s->spline_lds, f32, c->stream));
+        if (staged)
+            LAUNCH(c, f32 ? "basis_f32" : "basis_f64",
+                   launch_basis(dseg + k, 1, segs[k].unit_count, s->spline_lds, f32, c->stream));
         if (ham)
             LAUNCH(c, kname(true, prec), launch_h(mode, dseg + k, 1, segs[k].item_count, c->stream));
         else

@@ -92,6 +92,7 @@ struct nao_server_s {
     nao_ctx home = nullptr;
     nao_precision prec = NAO_FP64;
     int32_t max_per_launch = 8;
+    int32_t group_max = 256;
     std::vector<Slot> slots;
     std::map<int64_t, Session> sessions;
     std::deque<int64_t> pending;            // sessions waiting for admission, in open order
@@ -135,6 +136,10 @@ nao_status admit(nao_server srv, Session& se)
     nao_status st = nao_build_batches(srv->home, &se.host.desc, (int64_t)se.host.w.size(), se.host.xyz.data(),
                                       se.host.w.data(), se.host.max_batch, &sys);
     if (st != NAO_OK) return st;
+    if (srv->group_max != 256 && (st = nao_system_set_group_max(sys, srv->group_max)) != NAO_OK) {
+        nao_system_destroy(sys);
+        return st;
+    }
     int64_t nb = 0, np = (int64_t)se.host.w.size();
     nao_system_info(sys, &nb, nullptr, nullptr, nullptr);
     void *D = nullptr, *H = nullptr, *v = nullptr, *n = nullptr;
@@ -253,19 +258,22 @@ nao_status dispatch(nao_server srv, Slot& sl)
 
 extern "C" {
 
-nao_status nao_server_create(nao_ctx home, int32_t n_slots, int32_t max_per_launch, nao_precision precision,
-                             nao_server* out)
+nao_status nao_server_create(nao_ctx home, int32_t n_slots, int32_t max_per_launch, int32_t group_max,
+                             nao_precision precision, nao_server* out)
 {
     if (!out || !home) return NAO_ERR_INVALID_ARG;
     *out = nullptr;
     if (n_slots < 1 || n_slots > 16 || max_per_launch < 1 || max_per_launch > 256)
         return (ctx_set_error(home, "n_slots outside [1, 16] or max_per_launch outside [1, 256]"), NAO_ERR_INVALID_ARG);
     if (precision < NAO_FP64 || precision > NAO_BF16X6) return (ctx_set_error(home, "bad precision"), NAO_ERR_INVALID_ARG);
+    if (group_max != 0 && (group_max < 16 || group_max > 256))
+        return (ctx_set_error(home, "group_max must be 0 or in [16, 256]"), NAO_ERR_INVALID_ARG);
     nao_server srv = new (std::nothrow) nao_server_s();
     if (!srv) return NAO_ERR_OUT_OF_MEMORY;
     srv->home = home;
     srv->prec = precision;
     srv->max_per_launch = max_per_launch;
+    srv->group_max = group_max;
     srv->slots.resize(n_slots);
     for (Slot& sl : srv->slots) {
         nao_status st = nao_ctx_create(ctx_device(home), nullptr, 0, &sl.ctx);

@@ -82,7 +82,7 @@ _sig("nao_integrate_h", _S, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_
 _sig("nao_update_density", _S, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int, _c_dp)
 _sig("nao_system_destroy", None, _vp)
 _sig("nao_run_many", _S, _vp, ctypes.POINTER(Work), ctypes.c_int64, ctypes.c_int, ctypes.c_uint32)
-_sig("nao_server_create", _S, _vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int, ctypes.POINTER(_vp))
+_sig("nao_server_create", _S, _vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int, ctypes.POINTER(_vp))
 _sig("nao_server_open_session", _S, _vp, ctypes.POINTER(BasisDesc), ctypes.c_int64, _c_dp, _c_dp, ctypes.c_int32,
      _c_i64p)
 _sig("nao_server_close_session", _S, _vp, ctypes.c_int64)
@@ -358,10 +358,10 @@ class Server:
     """nao_server: sessions admitted by the home context's HBM budget, n_slots stream slots,
     continuous batching of (density, Hamiltonian) iteration requests."""
 
-    def __init__(self, home, n_slots=2, max_per_launch=8, precision="fp64"):
+    def __init__(self, home, n_slots=2, max_per_launch=8, precision="fp64", group_max=256):
         h = _vp()
-        _check(_lib.nao_server_create(home.handle, int(n_slots), int(max_per_launch), PRECISIONS[precision],
-                                      ctypes.byref(h)), home.handle)
+        _check(_lib.nao_server_create(home.handle, int(n_slots), int(max_per_launch), int(group_max),
+                                      PRECISIONS[precision], ctypes.byref(h)), home.handle)
         self.home = home
         self.handle = h
         self._keep = {}

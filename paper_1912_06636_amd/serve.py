@@ -77,7 +77,7 @@ def run(nao, torch, pool, lam, duration_s, max_requests, path, precision="bf16x3
     rng = np.random.default_rng(np.random.SeedSequence([5, seed, g.STREAM_ARRIVAL, int(lam * 1000)]))
     home = nao.Context(0, hbm_budget=hbm_budget)
     if path == "plain":
-        srv = nao.Server(home, n_slots=1, max_per_launch=1, precision="fp64")
+        srv = nao.Server(home, n_slots=1, max_per_launch=1, precision="fp64", group_max=0)
     else:
         srv = nao.Server(home, n_slots=n_slots, max_per_launch=max_per_launch, precision=precision)
     stager = DensityStager(torch, dev)
@@ -153,3 +153,52 @@ def run(nao, torch, pool, lam, duration_s, max_requests, path, precision="bf16x3
     if log:
         log("serve %s" % out)
     return out
+
+
+def main(argv=None):
+    """python -m paper_1912_06636_amd.serve: one JSON line per (path, arrival rate)."""
+    import argparse
+    import json
+    import sys
+
+    import torch
+
+    from paper_1912_06636_amd import nao
+
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--lam", type=float, nargs="+", default=[2.0, 8.0, 32.0])
+    ap.add_argument("--seconds", type=float, default=30.0)
+    ap.add_argument("--max-requests", type=int, default=500)
+    ap.add_argument("--paths", nargs="+", default=["plain", "batched"])
+    ap.add_argument("--precision", default="bf16x6")
+    ap.add_argument("--pool", type=int, default=6)
+    ap.add_argument("--grid-scale", type=float, default=1.0)
+    ap.add_argument("--hbm-budget-gb", type=float, default=0.0)
+    ap.add_argument("--slots", type=int, default=3)
+    ap.add_argument("--max-per-launch", type=int, default=8)
+    args = ap.parse_args(argv)
+
+    def log(msg):
+        print("[serve]", msg, file=sys.stderr, flush=True)
+
+    t0 = time.time()
+    pool = make_pool(args.pool, grid_scale=args.grid_scale)
+    # work measure per request (both operations use the same batches)
+    home = nao.Context(0)
+    for w in pool:
+        s = nao.build_batches(home, w["basis"], w["xyz"], w["w"], w["max_batch"])
+        w["units"] = s.work_units()
+        s.close()
+    home.close()
+    log("pool of %d structures (%s atoms) ready in %.1f s" % (
+        len(pool), [len(w["basis"]["atom_xyz"]) for w in pool], time.time() - t0))
+    for path in args.paths:
+        for lam in args.lam:
+            out = run(nao, torch, pool, lam, args.seconds, args.max_requests, path, precision=args.precision,
+                      n_slots=args.slots, max_per_launch=args.max_per_launch,
+                      hbm_budget=int(args.hbm_budget_gb * (1 << 30)), log=log)
+            print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

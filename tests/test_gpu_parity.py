@@ -116,7 +116,7 @@ def test_identities_on_gpu_outputs(nao, ctx):
     s.close()
 
 
-@pytest.mark.parametrize("group_max", [16, 48, 128, 256])
+@pytest.mark.parametrize("group_max", [0, 16, 48, 128, 256])
 def test_grouping_invariance(nao, ctx, group_max):
     """P7 on the GPU: execution grouping changes only summation order."""
     w, B, ref = case("multitile")
