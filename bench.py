@@ -98,6 +98,7 @@ def main():
     ap.add_argument("--workload", default="slab375", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="fp64")
     ap.add_argument("--group-max", type=int, default=256)
+    ap.add_argument("--h-tile", type=int, default=64, help="Hamiltonian tile width (64 or 128)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--calibrate-copy", type=int, default=0,
@@ -123,6 +124,8 @@ def main():
     sysm = nao.build_batches(ctx, work["basis"], work["xyz"], work["w"], work["max_batch"])
     if args.group_max != 256:
         sysm.set_group_max(args.group_max)
+    if args.h_tile != 64:
+        sysm.set_h_tile(args.h_tile)
     log("system built in %.1f s: %d batches, N_b=%d" % (time.time() - t0, sysm.n_batches, sysm.n_basis))
     perm, bp, lp, li, Bsz, msz = batch_measures(sysm)
     U = float(np.sum(Bsz * msz * msz))
@@ -209,7 +212,7 @@ def main():
         "data": "synthetic (seeded generator; shapes of the paper's workloads)",
         "config": {"workload": args.workload, "description": desc, "n_points": int(sysm.n_points),
                    "n_basis": int(sysm.n_basis), "n_batches": int(sysm.n_batches), "units_per_op": U,
-                   "group_max": args.group_max, "precision": prec},
+                   "group_max": args.group_max, "h_tile": args.h_tile, "precision": prec},
         "latency_ms": {"p50": round(float(np.percentile(step_ms, 50)), 3),
                        "p99": round(float(np.percentile(step_ms, 99)), 3)},
         "ops_ms": {"density": round(float(np.mean(n_ms)), 3), "hamiltonian": round(float(np.mean(h_ms)), 3)},

@@ -159,6 +159,11 @@ nao_status nao_build_batches(nao_ctx ctx, const nao_basis_desc* basis, int64_t n
  * every octree batch as its own unit (no packing).  Results change only by floating-point
  * summation order. */
 nao_status nao_system_set_group_max(nao_system sys, int32_t group_max);
+/* Tile width (64 or 128 basis functions) of the Hamiltonian kernel for this system; wider
+ * tiles stage each basis value for twice the MFMA work, narrower ones waste less padding.
+ * Results change only by floating-point summation order.  The reduced-precision split-BF16
+ * modes always use 64. */
+nao_status nao_system_set_h_tile(nao_system sys, int32_t h_tile);
 nao_status nao_system_info(nao_system sys, int64_t* n_basis, int64_t* n_batches, int64_t* n_list,
                            size_t* dev_bytes);
 /* Host copies of the system's batches and lists (as nao_plan_get_batches). */

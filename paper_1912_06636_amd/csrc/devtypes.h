@@ -93,8 +93,9 @@ enum Mode { MODE_FP64 = 0, MODE_FP32 = 1, MODE_BF16X3 = 2, MODE_BF16X6 = 3 };
 // cover the largest table of the systems in the segment list.
 hipError_t launch_basis(const DevSeg* segs_dev, int n_segs, int64_t n_units, int spline_lds, bool fp32_out,
                         hipStream_t st, int64_t max_grid = 0);
+// h_tile: 64, or 128 for the wide FP64/FP32 kernels (items then index 128-wide tiles).
 hipError_t launch_h(Mode mode, const DevSeg* segs_dev, int n_segs, int64_t n_items, hipStream_t st,
-                    int64_t max_grid = 0);
+                    int64_t max_grid = 0, int h_tile = TILE);
 hipError_t launch_n(Mode mode, const DevSeg* segs_dev, int n_segs, int64_t n_items, hipStream_t st,
                     int64_t max_grid = 0);
 hipError_t launch_fill(double* p, int64_t n, double value, hipStream_t st);

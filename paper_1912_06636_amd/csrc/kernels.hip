@@ -464,6 +464,108 @@ __global__ __launch_bounds__(256) void h_kernel(const DevSeg* __restrict__ segs,
     }
 }
 
+// Hamiltonian with 128x128 tile pairs: eight waves, each a 32x64 block (2x4 MFMA blocks), so
+// that every staged basis value feeds twice as many MFMAs as in the 64-wide kernel.  Chunks
+// of 16 points, double-buffered as above.
+constexpr int WTILE = 128;
+
+template <typename T>
+__global__ __launch_bounds__(512) void h_kernel_wide(const DevSeg* __restrict__ segs, int n_segs, int64_t total)
+{
+    typedef Mma<T> M;
+    __shared__ T As[2][KCHUNK][WTILE + 2];
+    __shared__ T Bs[2][KCHUNK][WTILE + 2];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = wave >> 1, wc = wave & 1;  // rows 32 wr .. 32 wr + 31, columns 64 wc .. 64 wc + 63
+    const int lr = lane & 15, lk = lane >> 4;
+    for (int64_t v_ = blockIdx.x; v_ < xcd_span(total); v_ += gridDim.x) {
+        const int64_t b = xcd_item(v_, total);
+        if (b >= total) continue;
+        const int s = find_segment(segs, n_segs, b, [](const DevSeg& g) { return g.item_prefix; });
+        const DevSeg& sg = segs[s];
+        const HItem it = static_cast<const HItem*>(sg.items)[sg.item_begin + (b - sg.item_prefix)];
+        const DevUnit u = sg.units[it.unit];
+        const T* __restrict__ phi = static_cast<const T*>(sg.phi) + u.out_offset;
+        const double* __restrict__ wv = sg.wv + u.point_begin;
+        const int np = u.n_points, ld = u.ld;
+        const int I0 = it.ti * WTILE, J0 = it.tj * WTILE;
+        const int n_chunks = (np + KCHUNK - 1) / KCHUNK;
+
+        T ra[4], rb[4];
+        auto fetch = [&](int c) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int e = tid + 512 * q;
+                const int r = e >> 7, col = e & 127;
+                const int p = c * KCHUNK + r;
+                T a = T(0), bb = T(0);
+                if (p < np) {
+                    const T* rowp = phi + (int64_t)p * ld;
+                    a = T((double)rowp[I0 + col] * wv[p]);
+                    bb = rowp[J0 + col];
+                }
+                ra[q] = a;
+                rb[q] = bb;
+            }
+        };
+        auto stash = [&](int buf) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int e = tid + 512 * q;
+                As[buf][e >> 7][e & 127] = ra[q];
+                Bs[buf][e >> 7][e & 127] = rb[q];
+            }
+        };
+
+        typename M::acc_t acc[2][4];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = M::zero();
+        fetch(0);
+        stash(0);
+        __syncthreads();
+        for (int c = 0; c < n_chunks; ++c) {
+            const int buf = c & 1;
+            if (c + 1 < n_chunks) fetch(c + 1);
+#pragma unroll
+            for (int kk = 0; kk < KCHUNK / 4; ++kk) {
+                const int kr = kk * 4 + lk;
+                T a[2], bq[4];
+#pragma unroll
+                for (int i = 0; i < 2; ++i) a[i] = As[buf][kr][wr * 32 + i * 16 + lr];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) bq[j] = Bs[buf][kr][wc * 64 + j * 16 + lr];
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) acc[i][j] = M::op(a[i], bq[j], acc[i][j]);
+            }
+            if (c + 1 < n_chunks) stash(buf ^ 1);
+            __syncthreads();
+        }
+
+        const int32_t* __restrict__ fn = sg.unit_fn + u.fn_begin;
+        double* __restrict__ H = sg.H;
+        const int64_t ldh = sg.ld;
+        const bool diag = it.ti == it.tj;
+#pragma unroll
+        for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+            for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = wr * 32 + ib * 16 + M::row(lk, r);
+                    const int col = wc * 64 + jb * 16 + lr;
+                    const int ci = I0 + row, cj = J0 + col;
+                    if (ci < u.m && cj < u.m && (!diag || row <= col)) {
+                        const int64_t gi = fn[ci], gj = fn[cj];
+                        unsafeAtomicAdd(H + gi * ldh + gj, (double)acc[ib][jb][r]);
+                    }
+                }
+    }
+}
+
 // Density: per work item one 64-wide column tile J of a unit,
 //   T[:, J] = sum_{I <= J} c_IJ Phi[:, I] D[I, J]   (c = 2 off the diagonal tile, 1 on it,
 //             the diagonal tile read from the upper triangle of D),
@@ -824,8 +926,17 @@ __global__ __launch_bounds__(256) void n_kernel_bf16(const DevSeg* __restrict__ 
 }
 
 hipError_t launch_h(Mode mode, const DevSeg* segs_dev, int n_segs, int64_t n_items, hipStream_t st,
-                    int64_t max_grid)
+                    int64_t max_grid, int h_tile)
 {
+    if (h_tile == WTILE && (mode == MODE_FP64 || mode == MODE_FP32)) {
+        if (n_items <= 0 || n_segs <= 0) return hipSuccess;
+        if (n_items > 0x7ffffff0) return hipErrorInvalidValue;
+        const dim3 g(grid_for(n_items, max_grid)), b(512);
+        if (mode == MODE_FP64) hipLaunchKernelGGL(h_kernel_wide<double>, g, b, 0, st, segs_dev, n_segs, n_items);
+        else hipLaunchKernelGGL(h_kernel_wide<float>, g, b, 0, st, segs_dev, n_segs, n_items);
+        return hipGetLastError();
+    }
+    if (h_tile != TILE) return hipErrorInvalidValue;
     if (n_items <= 0 || n_segs <= 0) return hipSuccess;
     if (n_items > 0x7ffffff0) return hipErrorInvalidValue;
     const dim3 g(grid_for(n_items, max_grid)), b(256);

@@ -203,7 +203,8 @@ namespace {
 
 struct Block {
     int64_t unit_begin = 0, unit_count = 0;
-    int64_t h_begin = 0, h_count = 0;
+    int64_t h_begin = 0, h_count = 0;    // Hamiltonian items over 64-wide tiles
+    int64_t hw_begin = 0, hw_count = 0;  // ... over 128-wide tiles (systems with h_tile 128)
     int64_t n_begin = 0, n_count = 0;
     int64_t phi_elems = 0;
 };
@@ -216,6 +217,7 @@ struct nao_system_s {
     int64_t n_points = 0;
     int32_t max_batch = 0;
     int32_t group_max = MAX_UNIT_POINTS;
+    int32_t h_tile = TILE;  // width of the Hamiltonian kernel's tiles (64 or 128)
     std::vector<int64_t> perm, batch_ptr, atom_ptr;
     std::vector<int32_t> atoms;
     double work_units = 0.0;
@@ -226,7 +228,7 @@ struct nao_system_s {
     DevSys dsys{};
     DevArray d_sys, d_px, d_py, d_pz, d_pw, d_perm, d_atoms, d_species, d_shell_ptr, d_shell_l, d_shell_rad,
         d_radial_par, d_spline, d_fn_ptr, d_fn_code;
-    DevArray d_units, d_unit_atoms, d_unit_cols, d_unit_fn, d_h_items, d_n_items;
+    DevArray d_units, d_unit_atoms, d_unit_cols, d_unit_fn, d_h_items, d_hw_items, d_n_items;
     DevArray d_wv, d_v, d_D, d_H, d_n, d_segs;
     int spline_lds = 0;  // doubles of spline table staged in LDS by the basis kernel (0 = not staged)
 };
@@ -238,7 +240,7 @@ size_t system_bytes(const nao_system_s* s)
     const DevArray* arr[] = {&s->d_sys, &s->d_px, &s->d_py, &s->d_pz, &s->d_pw, &s->d_perm, &s->d_atoms,
                              &s->d_species, &s->d_shell_ptr, &s->d_shell_l, &s->d_shell_rad, &s->d_radial_par,
                              &s->d_spline, &s->d_fn_ptr, &s->d_fn_code, &s->d_units, &s->d_unit_atoms, &s->d_unit_cols, &s->d_unit_fn,
-                             &s->d_h_items, &s->d_n_items, &s->d_wv, &s->d_v, &s->d_D, &s->d_H, &s->d_n,
+                             &s->d_h_items, &s->d_hw_items, &s->d_n_items, &s->d_wv, &s->d_v, &s->d_D, &s->d_H, &s->d_n,
                              &s->d_segs};
     size_t t = 0;
     for (auto* a : arr) t += a->bytes;
@@ -250,7 +252,7 @@ void free_all(nao_system_s* s)
     DevArray* arr[] = {&s->d_sys, &s->d_px, &s->d_py, &s->d_pz, &s->d_pw, &s->d_perm, &s->d_atoms,
                        &s->d_species, &s->d_shell_ptr, &s->d_shell_l, &s->d_shell_rad, &s->d_radial_par,
                        &s->d_spline, &s->d_fn_ptr, &s->d_fn_code, &s->d_units, &s->d_unit_atoms, &s->d_unit_cols, &s->d_unit_fn,
-                       &s->d_h_items, &s->d_n_items, &s->d_wv, &s->d_v, &s->d_D, &s->d_H, &s->d_n, &s->d_segs};
+                       &s->d_h_items, &s->d_hw_items, &s->d_n_items, &s->d_wv, &s->d_v, &s->d_D, &s->d_H, &s->d_n, &s->d_segs};
     for (auto* a : arr) {
         dev_free(s->ctx, a->p, a->bytes);
         a->p = nullptr;
@@ -269,7 +271,7 @@ nao_status build_groups(nao_system_s* s)
     make_groups(s->basis, s->batch_ptr, s->atom_ptr, s->atoms, s->group_max, units, uat, ucol);
     std::vector<DevUnit> du(units.size());
     std::vector<int32_t> ufn;
-    std::vector<HItem> hitems;
+    std::vector<HItem> hitems, hwitems;
     std::vector<NItem> nitems;
     s->blocks.clear();
     Block cur;
@@ -284,7 +286,7 @@ nao_status build_groups(nao_system_s* s)
         d.n_points = u.n_points;
         d.n_atoms = u.n_atoms;
         d.m = u.m;
-        d.ld = round_up(u.m, TILE);
+        d.ld = round_up(u.m, std::max<int32_t>(TILE, s->h_tile));
         for (int32_t q = 0; q < u.n_atoms; ++q) {
             const int32_t a = uat[u.atom_begin + q];
             for (int64_t f = s->basis.atom_first[a]; f < s->basis.atom_first[a + 1]; ++f) ufn.push_back((int32_t)f);
@@ -296,6 +298,7 @@ nao_status build_groups(nao_system_s* s)
             cur = Block();
             cur.unit_begin = (int64_t)k;
             cur.h_begin = (int64_t)hitems.size();
+            cur.hw_begin = (int64_t)hwitems.size();
             cur.n_begin = (int64_t)nitems.size();
             off = 0;
         }
@@ -303,12 +306,18 @@ nao_status build_groups(nao_system_s* s)
         off += elems;
         cur.phi_elems = off;
         cur.unit_count++;
-        const int nt = d.ld / TILE;
+        const int nt = (d.m + TILE - 1) / TILE;  // tiles that hold at least one column
         for (int tj = 0; tj < nt; ++tj) {
             for (int ti = 0; ti <= tj; ++ti) hitems.push_back(HItem{(int32_t)k, (int16_t)ti, (int16_t)tj});
             nitems.push_back(NItem{(int32_t)k, tj});
         }
+        if (s->h_tile == 128) {
+            const int ntw = (d.m + 127) / 128;
+            for (int tj = 0; tj < ntw; ++tj)
+                for (int ti = 0; ti <= tj; ++ti) hwitems.push_back(HItem{(int32_t)k, (int16_t)ti, (int16_t)tj});
+        }
         cur.h_count = (int64_t)hitems.size() - cur.h_begin;
+        cur.hw_count = (int64_t)hwitems.size() - cur.hw_begin;
         cur.n_count = (int64_t)nitems.size() - cur.n_begin;
     }
     if (cur.unit_count) s->blocks.push_back(cur);
@@ -322,6 +331,7 @@ nao_status build_groups(nao_system_s* s)
     if ((st = upload(c, s->d_unit_cols, ucol.data(), ucol.size() * sizeof(int32_t))) != NAO_OK) return st;
     if ((st = upload(c, s->d_unit_fn, ufn.data(), ufn.size() * sizeof(int32_t))) != NAO_OK) return st;
     if ((st = upload(c, s->d_h_items, hitems.data(), hitems.size() * sizeof(HItem))) != NAO_OK) return st;
+    if ((st = upload(c, s->d_hw_items, hwitems.data(), hwitems.size() * sizeof(HItem))) != NAO_OK) return st;
     if ((st = upload(c, s->d_n_items, nitems.data(), nitems.size() * sizeof(NItem))) != NAO_OK) return st;
     if ((st = ensure(c, s->d_segs, std::max<size_t>(1, s->blocks.size()) * sizeof(DevSeg))) != NAO_OK) return st;
     size_t need = 0;
@@ -339,7 +349,9 @@ nao_status build_groups(nao_system_s* s)
     return NAO_OK;
 }
 
-DevSeg make_seg(const nao_system_s* s, const Block& b, bool ham)
+// Hamiltonian segments use the 128-wide items when wide is set (FP64 / FP32 on systems with
+// h_tile 128), else the 64-wide ones.
+DevSeg make_seg(const nao_system_s* s, const Block& b, bool ham, bool wide = false)
 {
     DevSeg g{};
     g.sys = s->d_sys.as<DevSys>();
@@ -347,14 +359,14 @@ DevSeg make_seg(const nao_system_s* s, const Block& b, bool ham)
     g.unit_atoms = s->d_unit_atoms.as<int32_t>();
     g.unit_cols = s->d_unit_cols.as<int32_t>();
     g.unit_fn = s->d_unit_fn.as<int32_t>();
-    g.items = ham ? (const void*)s->d_h_items.p : (const void*)s->d_n_items.p;
+    g.items = ham ? (wide ? (const void*)s->d_hw_items.p : (const void*)s->d_h_items.p) : (const void*)s->d_n_items.p;
     g.phi = s->ctx->scratch;
     g.ld = s->basis.n_basis;
     g.unit_begin = b.unit_begin;
     g.unit_count = b.unit_count;
     g.unit_prefix = 0;
-    g.item_begin = ham ? b.h_begin : b.n_begin;
-    g.item_count = ham ? b.h_count : b.n_count;
+    g.item_begin = ham ? (wide ? b.hw_begin : b.h_begin) : b.n_begin;
+    g.item_count = ham ? (wide ? b.hw_count : b.h_count) : b.n_count;
     g.item_prefix = 0;
     return g;
 }
@@ -385,8 +397,8 @@ static const char* kname(bool ham, nao_precision p)
 struct ManyPlan {
     std::vector<const void*> key;  // precision, then (sys, op, in, out) per entry
     struct Chunk {
-        size_t all_off = 0, all_n = 0, h_off = 0, h_n = 0, n_off = 0, n_n = 0;
-        int64_t units = 0, h_items = 0, n_items = 0;
+        size_t all_off = 0, all_n = 0, h_off[2] = {0, 0}, h_n[2] = {0, 0}, n_off = 0, n_n = 0;
+        int64_t units = 0, h_items[2] = {0, 0}, n_items = 0;  // H lists: 64- and 128-wide tiles
     };
     std::vector<Chunk> chunks;
     std::vector<DevSeg> segs;
@@ -469,7 +481,7 @@ nao_status many_build(nao_ctx c, const nao_work* work, int64_t n_work, nao_preci
     }
     // one segment per (entry, block); consecutive segments share a chunk while their basis
     // values fit the scratch
-    struct Pending { DevSeg g; bool ham; int64_t phi; };
+    struct Pending { DevSeg g; bool ham; int64_t phi; int32_t h_tile; };
     std::vector<std::vector<Pending>> chunks(1);
     int64_t off = 0;
     for (size_t e = 0; e < m->entries.size(); ++e) {
@@ -481,7 +493,8 @@ nao_status many_build(nao_ctx c, const nao_work* work, int64_t n_work, nao_preci
                 chunks.emplace_back();
                 off = 0;
             }
-            DevSeg g = make_seg(s, b, ham);
+            const bool wide = ham && s->h_tile == 128 && (prec == NAO_FP64 || prec == NAO_FP32);
+            DevSeg g = make_seg(s, b, ham, wide);
             if (ham) {
                 g.wv = m->d_wv.as<double>() + m->wv_off[e];
                 g.H = const_cast<double*>(w.out);
@@ -489,7 +502,7 @@ nao_status many_build(nao_ctx c, const nao_work* work, int64_t n_work, nao_preci
                 g.D = w.in;
                 g.n = w.out;
             }
-            chunks.back().push_back(Pending{g, ham, off});
+            chunks.back().push_back(Pending{g, ham, off, wide ? 128 : TILE});
             off += b.phi_elems;
         }
     }
@@ -507,21 +520,22 @@ nao_status many_build(nao_ctx c, const nao_work* work, int64_t n_work, nao_preci
             m->segs.push_back(g);
         }
         k.all_n = m->segs.size() - k.all_off;
-        for (int pass = 0; pass < 2; ++pass) {
-            const bool ham = pass == 0;
+        for (int pass = 0; pass < 3; ++pass) {  // H with 64-wide tiles, H with 128-wide, density
+            const bool ham = pass < 2;
+            const int want_tile = pass == 1 ? 128 : TILE;
             const size_t o = m->segs.size();
             int64_t items = 0;
             for (size_t q = 0; q < k.all_n; ++q) {
-                if (ch[q].ham != ham) continue;
+                if (ch[q].ham != ham || (ham && ch[q].h_tile != want_tile)) continue;
                 DevSeg g = m->segs[k.all_off + q];
                 g.item_prefix = items;
                 items += g.item_count;
                 m->segs.push_back(g);
             }
             if (ham) {
-                k.h_off = o;
-                k.h_n = m->segs.size() - o;
-                k.h_items = items;
+                k.h_off[pass] = o;
+                k.h_n[pass] = m->segs.size() - o;
+                k.h_items[pass] = items;
             } else {
                 k.n_off = o;
                 k.n_n = m->segs.size() - o;
@@ -566,7 +580,10 @@ nao_status many_enqueue(nao_ctx c, ManyPlan* m)
         if (staged)
             LAUNCH(c, f32 ? "basis_f32" : "basis_f64",
                    launch_basis(d + k.all_off, (int)k.all_n, k.units, lds, f32, c->stream, grid));
-        if (k.h_n) LAUNCH(c, kname(true, m->prec), launch_h(mode, d + k.h_off, (int)k.h_n, k.h_items, c->stream, grid));
+        for (int t = 0; t < 2; ++t)
+            if (k.h_n[t])
+                LAUNCH(c, kname(true, m->prec), launch_h(mode, d + k.h_off[t], (int)k.h_n[t], k.h_items[t], c->stream,
+                                                         grid, t == 0 ? TILE : 128));
         if (k.n_n) LAUNCH(c, kname(false, m->prec), launch_n(mode, d + k.n_off, (int)k.n_n, k.n_items, c->stream, grid));
     }
     for (const nao_work& w : m->entries)
@@ -1071,6 +1088,24 @@ nao_status nao_system_set_group_max(nao_system s, int32_t group_max)
     }
 }
 
+nao_status nao_system_set_h_tile(nao_system s, int32_t h_tile)
+{
+    if (!s) return (g_thread_error = "system is NULL", NAO_ERR_INVALID_ARG);
+    nao_status st = check_ctx(s->ctx);
+    if (st != NAO_OK) return st;
+    if (h_tile != 64 && h_tile != 128) return (set_err(s->ctx, "h_tile must be 64 or 128"), NAO_ERR_INVALID_ARG);
+    if (h_tile == s->h_tile) return NAO_OK;
+    HIP_TRY(s->ctx, hipStreamSynchronize(s->ctx->stream));
+    many_forget(s->ctx, s);
+    s->h_tile = h_tile;
+    try {
+        return build_groups(s);
+    } catch (...) {
+        set_err(s->ctx, "internal error in nao_system_set_h_tile");
+        return NAO_ERR_INTERNAL;
+    }
+}
+
 nao_status nao_system_info(nao_system s, int64_t* n_basis, int64_t* n_batches, int64_t* n_list, size_t* dev_bytes)
 {
     if (!s) return (g_thread_error = "system is NULL", NAO_ERR_INVALID_ARG);
@@ -1212,8 +1247,9 @@ static nao_status run_blocks(nao_system s, bool ham, nao_precision prec, const d
     const bool staged = true;  // every mode reads its basis values from the scratch block
     nao_ctx c = s->ctx;
     std::vector<DevSeg> segs;
+    const bool wide = ham && s->h_tile == 128 && (prec == NAO_FP64 || prec == NAO_FP32);
     for (const Block& b : s->blocks) {
-        DevSeg g = make_seg(s, b, ham);
+        DevSeg g = make_seg(s, b, ham, wide);
         g.wv = wv;
         g.D = D;
         g.H = H;
@@ -1229,7 +1265,8 @@ static nao_status run_blocks(nao_system s, bool ham, nao_precision prec, const d
             LAUNCH(c, f32 ? "basis_f32" : "basis_f64",
                    launch_basis(dseg + k, 1, segs[k].unit_count, s->spline_lds, f32, c->stream));
         if (ham)
-            LAUNCH(c, kname(true, prec), launch_h(mode, dseg + k, 1, segs[k].item_count, c->stream));
+            LAUNCH(c, kname(true, prec),
+                   launch_h(mode, dseg + k, 1, segs[k].item_count, c->stream, 0, wide ? 128 : TILE));
         else
             LAUNCH(c, kname(false, prec), launch_n(mode, dseg + k, 1, segs[k].item_count, c->stream));
     }

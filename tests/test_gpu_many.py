@@ -102,3 +102,19 @@ def test_many_matches_oracle_member(env):
     assert rel_max(H1.cpu().numpy(), ref["H"]) <= 1e-12
     assert rel_max(n1.cpu().numpy(), ref["n"]) <= 1e-12
     s1.close()
+
+
+def test_many_with_wide_tiles(env):
+    """Systems with 64- and 128-wide Hamiltonian tiles in one launch sequence."""
+    nao, ctx, structs, torch = env
+    say("run_many wide tiles")
+    structs[1][1].set_h_tile(128)
+    structs[3][1].set_h_tile(128)
+    tens = [_tensors(torch, w, s) for w, s in structs]
+    work = [(s, "h", v, H) for (w, s), (v, D, H, n) in zip(structs, tens)]
+    ctx.run_many(work, capture_graph=True)
+    ctx.synchronize()
+    for (w, s), (v, D, H, n) in zip(structs, tens):
+        assert rel_max(H.cpu().numpy(), s.integrate_h(w["v"])) <= 1e-12
+    structs[1][1].set_h_tile(64)
+    structs[3][1].set_h_tile(64)

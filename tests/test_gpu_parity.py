@@ -223,3 +223,24 @@ def test_reduced_precision_error(nao, ctx, name, prec):
     tol = PREC_TOL[prec]
     assert eH <= tol and en <= tol and eN <= tol
     s.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("name", ["config1", "multitile"])
+def test_wide_hamiltonian_tiles(nao, ctx, name, prec):
+    """128-wide Hamiltonian tiles give the same H (FP64: within 1e-12 of the oracle; other
+    modes: equal to the 64-wide result within their own error)."""
+    w, B, ref = case(name)
+    say("h_tile 128", name, prec)
+    s = nao.build_batches(ctx, w["basis"], w["xyz"], w["w"], w["max_batch"])
+    H64 = s.integrate_h(w["v"], precision=prec)
+    n64 = s.update_density(w["D"], precision=prec)
+    s.set_h_tile(128)
+    H128 = s.integrate_h(w["v"], precision=prec)
+    n128 = s.update_density(w["D"], precision=prec)
+    assert np.array_equal(H128, H128.T)
+    if prec == "fp64":
+        assert rel_max(H128, ref["H"]) <= TOL and rel_max(n128, ref["n"]) <= TOL
+    else:
+        assert rel_max(H128, H64) <= 1e-5 and rel_max(n128, n64) <= 1e-12
+    s.close()
