@@ -35,6 +35,9 @@ WORKLOADS = {
                     "cutoff), 50x302 grid/atom = 1,510,000 points, octree batches <= 256"),
     "cube8": (1, "8 atoms in a 6 A cube, 5 NAO/atom (40 basis functions), 30x110 grid/atom = "
                  "26,400 points, octree batches <= 200"),
+    "many64": (3, "64 independent structures, 10-200 atoms log-uniform on a jittered simple-cubic "
+                  "lattice, 14 NAO/atom, 50x302 grid/atom, octree batches <= 256, all in one "
+                  "hipGraph-captured launch sequence (nao_run_many)"),
 }
 
 
@@ -90,6 +93,78 @@ def cpu_baseline(work, perm, bp, lp, li, budget_s):
     return rate, cores, desc
 
 
+def bench_many(args, desc):
+    """64 structures per step through one captured launch sequence (config-3 shapes)."""
+    import torch
+    from paper_1912_06636_amd import nao
+    from workloads import config_workload
+    from workloads.generate import CONFIG3_N_STRUCTURES
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)
+    ctx = nao.Context(0, stream=stream.cuda_stream)
+    t0 = time.time()
+    systems, tens, U = [], [], 0.0
+    for k in range(CONFIG3_N_STRUCTURES):
+        w = config_workload(3, k)
+        sysm = nao.build_batches(ctx, w["basis"], w["xyz"], w["w"], w["max_batch"])
+        if k == 0 and not args.h_tile:
+            ht, gm, ms = sysm.autotune(w["v"], w["D"], precision=args.precision, force=True)
+            log("autotuned on structure 0: h_tile %d, group_max %d" % (ht, gm))
+        elif not args.h_tile:
+            sysm.autotune(w["v"], w["D"], precision=args.precision)
+        U += sysm.work_units()
+        with torch.cuda.stream(stream):
+            t = (torch.from_numpy(w["v"]).to(dev), torch.from_numpy(w["D"]).to(dev),
+                 torch.empty((sysm.n_basis, sysm.n_basis), dtype=torch.float64, device=dev),
+                 torch.empty(sysm.n_points, dtype=torch.float64, device=dev))
+        systems.append(sysm)
+        tens.append(t)
+    torch.cuda.synchronize()
+    log("%d structures built in %.1f s (U = %.3g per operation)" % (len(systems), time.time() - t0, U))
+    work = []
+    for sysm, (v, D, H, n) in zip(systems, tens):
+        work += [(sysm, "n", D, n), (sysm, "h", v, H)]
+
+    def timed(fn, steps):
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            ev0.record(stream)
+            for _ in range(steps):
+                fn()
+            ev1.record(stream)
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / steps
+
+    def separate():
+        for sysm, (v, D, H, n) in zip(systems, tens):
+            sysm.update_density(D, precision=args.precision, out=n)
+            sysm.integrate_h(v, precision=args.precision, out=H)
+
+    for _ in range(args.warmup):
+        ctx.run_many(work, precision=args.precision, capture_graph=True)
+    ms_graph = timed(lambda: ctx.run_many(work, precision=args.precision, capture_graph=True), args.steps)
+    ms_eager = timed(lambda: ctx.run_many(work, precision=args.precision, capture_graph=False), max(1, args.steps // 2))
+    ms_sep = timed(separate, max(1, args.steps // 2))
+    value = 2.0 * U / (ms_graph * 1e-3) / 1e9
+    log("graph %.2f ms, eager run_many %.2f ms, separate calls %.2f ms" % (ms_graph, ms_eager, ms_sep))
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "Gpt·basis²/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_graph, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3", "bf16x6": "bf16x6"}[args.precision],
+        "data": "synthetic (seeded generator; shapes of the paper's workloads)",
+        "config": {"workload": "many64", "description": desc, "structures": len(systems), "units_per_op": U,
+                   "precision": args.precision},
+        "ms_eager_run_many": round(ms_eager, 3), "ms_separate_calls": round(ms_sep, 3),
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+    for sysm in systems:
+        sysm.close()
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -98,7 +173,7 @@ def main():
     ap.add_argument("--workload", default="slab375", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="fp64")
     ap.add_argument("--group-max", type=int, default=256)
-    ap.add_argument("--h-tile", type=int, default=64, help="Hamiltonian tile width (64 or 128)")
+    ap.add_argument("--h-tile", type=int, default=0, help="Hamiltonian tile width (64 or 128); 0 = autotune")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--calibrate-copy", type=int, default=0,
@@ -114,6 +189,8 @@ def main():
     from workloads import config_workload
 
     cfg, desc = WORKLOADS[args.workload]
+    if args.workload == "many64":
+        return bench_many(args, desc)
     t0 = time.time()
     work = config_workload(cfg)
     log("workload %s generated in %.1f s" % (args.workload, time.time() - t0))
@@ -124,7 +201,7 @@ def main():
     sysm = nao.build_batches(ctx, work["basis"], work["xyz"], work["w"], work["max_batch"])
     if args.group_max != 256:
         sysm.set_group_max(args.group_max)
-    if args.h_tile != 64:
+    if args.h_tile:
         sysm.set_h_tile(args.h_tile)
     log("system built in %.1f s: %d batches, N_b=%d" % (time.time() - t0, sysm.n_batches, sysm.n_basis))
     perm, bp, lp, li, Bsz, msz = batch_measures(sysm)
@@ -136,6 +213,12 @@ def main():
         H = torch.empty((sysm.n_basis, sysm.n_basis), dtype=torch.float64, device=dev)
         n = torch.empty(sysm.n_points, dtype=torch.float64, device=dev)
     torch.cuda.synchronize()
+    tuned = None
+    if not args.h_tile:
+        t0 = time.time()
+        ht, gm, ms = sysm.autotune(v, D, precision=args.precision, force=True)
+        tuned = {"h_tile": ht, "group_max": gm, "best_ms": round(ms, 3)}
+        log("autotuned in %.1f s: %s" % (time.time() - t0, tuned))
 
     def step():
         sysm.update_density(D, precision=args.precision, out=n)
@@ -212,7 +295,8 @@ def main():
         "data": "synthetic (seeded generator; shapes of the paper's workloads)",
         "config": {"workload": args.workload, "description": desc, "n_points": int(sysm.n_points),
                    "n_basis": int(sysm.n_basis), "n_batches": int(sysm.n_batches), "units_per_op": U,
-                   "group_max": args.group_max, "h_tile": args.h_tile, "precision": prec},
+                   "group_max": args.group_max, "h_tile": args.h_tile, "precision": prec,
+                   "autotuned": tuned},
         "latency_ms": {"p50": round(float(np.percentile(step_ms, 50)), 3),
                        "p99": round(float(np.percentile(step_ms, 99)), 3)},
         "ops_ms": {"density": round(float(np.mean(n_ms)), 3), "hamiltonian": round(float(np.mean(h_ms)), 3)},

@@ -164,6 +164,18 @@ nao_status nao_system_set_group_max(nao_system sys, int32_t group_max);
  * Results change only by floating-point summation order.  The reduced-precision split-BF16
  * modes always use 64. */
 nao_status nao_system_set_h_tile(nao_system sys, int32_t h_tile);
+/* Autotuner: times a density update and a Hamiltonian integration of this system (inputs v and
+ * D in `space`) at `precision` for each candidate (Hamiltonian tile width 64 / 128, execution
+ * groups of 256 / 192 / 128 points; 64-wide only for split-BF16), keeps the fastest and
+ * applies it.  The choice is cached in a JSON file ($NAO_TUNE_CACHE, default
+ * $HOME/.cache/nao_tune.json) keyed by device, precision and the system's shape class
+ * (work-weighted mean list length and mean batch size of its octree batches); a cached class
+ * is applied without timing unless NAO_TUNE_FORCE is set.  Outputs (nullable): the chosen
+ * h_tile and group_max, and the best measured milliseconds (-1 when taken from the cache). */
+#define NAO_TUNE_FORCE 1u
+nao_status nao_system_autotune(nao_system sys, nao_precision precision, const double* v, const double* D,
+                               nao_memspace space, uint32_t flags, int32_t* h_tile, int32_t* group_max,
+                               double* best_ms);
 nao_status nao_system_info(nao_system sys, int64_t* n_basis, int64_t* n_batches, int64_t* n_list,
                            size_t* dev_bytes);
 /* Host copies of the system's batches and lists (as nao_plan_get_batches). */

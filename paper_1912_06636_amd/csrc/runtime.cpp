@@ -5,11 +5,15 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <map>
 #include <new>
 #include <string>
 #include <vector>
 
 #include <hip/hip_runtime_api.h>
+#include <sys/stat.h>
+#include <unistd.h>
 
 #include "devtypes.h"
 #include "internal.h"
@@ -54,7 +58,8 @@ struct nao_ctx_s {
     std::vector<Rec> recs;
     std::vector<hipEvent_t> pool;
     int n_cu = 256;
-    int64_t persistent_per_cu = 4;       // workgroups per CU of a multi-structure launch
+    int64_t persistent_per_cu = 0;       // workgroups per CU of a multi-structure launch (0 = one
+                                         // workgroup per item, dispatched by the hardware)
     std::vector<struct ManyPlan*> many;  // launch plans of nao_run_many (captured graphs)
     std::vector<std::pair<hipEvent_t, struct ManyPlan*>> inflight;  // eager plans still running
 };
@@ -715,7 +720,7 @@ nao_status nao_ctx_create(int device, void* hip_stream, size_t hbm_budget_bytes,
     }
     if (const char* e = std::getenv("NAO_PERSISTENT_PER_CU")) {
         const long v = std::atol(e);
-        if (v >= 1 && v <= 64) c->persistent_per_cu = v;
+        if (v >= 0 && v <= 64) c->persistent_per_cu = v;
     }
     c->scratch_cap_elems = scratch_cap_from_env();
     e = hipSetDevice(device);
@@ -1372,3 +1377,186 @@ nao_status nao_run_many(nao_ctx c, const nao_work* work, int64_t n_work, nao_pre
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------------------------------
+// autotuner: (Hamiltonian tile width, execution-group size) per device, precision and shape
+
+namespace {
+
+std::string tune_cache_path()
+{
+    if (const char* p = std::getenv("NAO_TUNE_CACHE")) return p;
+    const char* home = std::getenv("HOME");
+    return std::string(home ? home : "/tmp") + "/.cache/nao_tune.json";
+}
+
+// {"key": [h_tile, group_max], ...}, one entry per line
+std::map<std::string, std::pair<int, int>> tune_load()
+{
+    std::map<std::string, std::pair<int, int>> out;
+    std::ifstream f(tune_cache_path());
+    std::string line;
+    while (std::getline(f, line)) {
+        const size_t q0 = line.find('"');
+        if (q0 == std::string::npos) continue;
+        const size_t q1 = line.find('"', q0 + 1);
+        if (q1 == std::string::npos) continue;
+        const size_t b0 = line.find('[', q1);
+        if (b0 == std::string::npos) continue;
+        int a = 0, b = 0;
+        if (std::sscanf(line.c_str() + b0 + 1, "%d , %d", &a, &b) == 2) out[line.substr(q0 + 1, q1 - q0 - 1)] = {a, b};
+    }
+    return out;
+}
+
+void tune_save(const std::map<std::string, std::pair<int, int>>& c)
+{
+    const std::string path = tune_cache_path();
+    for (size_t k = 1; k < path.size(); ++k)
+        if (path[k] == '/') (void)::mkdir(path.substr(0, k).c_str(), 0755);
+    const std::string tmp = path + ".tmp" + std::to_string((long)::getpid());
+    {
+        std::ofstream f(tmp);
+        if (!f) return;
+        f << "{\n";
+        size_t k = 0;
+        for (const auto& kv : c)
+            f << "  \"" << kv.first << "\": [" << kv.second.first << ", " << kv.second.second << "]"
+              << (++k < c.size() ? ",\n" : "\n");
+        f << "}\n";
+    }
+    std::rename(tmp.c_str(), path.c_str());
+}
+
+// Shape class of a system: device, precision, work-weighted mean list length and mean batch
+// size of its octree batches (both bucketed), batch-size limit.
+std::string tune_key(nao_system s, nao_precision prec)
+{
+    hipDeviceProp_t prop;
+    std::string dev = "gpu";
+    if (hipGetDeviceProperties(&prop, s->ctx->device) == hipSuccess)
+        dev = std::string(prop.gcnArchName).substr(0, std::string(prop.gcnArchName).find(':')) + "x" +
+              std::to_string(prop.multiProcessorCount);
+    double bm2 = 0.0, bm = 0.0, pts = 0.0, nb = 0.0;
+    for (size_t b = 0; b + 1 < s->batch_ptr.size(); ++b) {
+        double m = 0.0;
+        for (int64_t q = s->atom_ptr[b]; q < s->atom_ptr[b + 1]; ++q)
+            m += (double)(s->basis.atom_first[s->atoms[q] + 1] - s->basis.atom_first[s->atoms[q]]);
+        if (m == 0.0) continue;
+        const double B = (double)(s->batch_ptr[b + 1] - s->batch_ptr[b]);
+        bm2 += B * m * m;
+        bm += B * m;
+        pts += B;
+        nb += 1.0;
+    }
+    const int mclass = bm > 0 ? (int)std::lround(bm2 / bm / 32.0) * 32 : 0;
+    const int bclass = nb > 0 ? (int)std::lround(pts / nb / 8.0) * 8 : 0;
+    static const char* pn[] = {"fp64", "fp32", "bf16x3", "bf16x6"};
+    return dev + "/" + pn[prec] + "/m" + std::to_string(mclass) + "/b" + std::to_string(bclass) + "/max" +
+           std::to_string(s->max_batch);
+}
+
+nao_status tune_apply(nao_system s, int h_tile, int group_max)
+{
+    nao_status st = NAO_OK;
+    if (s->group_max != group_max && (st = nao_system_set_group_max(s, group_max)) != NAO_OK) return st;
+    if (s->h_tile != h_tile && (st = nao_system_set_h_tile(s, h_tile)) != NAO_OK) return st;
+    return NAO_OK;
+}
+
+}  // namespace
+
+extern "C" nao_status nao_system_autotune(nao_system s, nao_precision prec, const double* v, const double* D,
+                                          nao_memspace space, uint32_t flags, int32_t* h_tile_out,
+                                          int32_t* group_max_out, double* best_ms)
+{
+    if (!s) return (g_thread_error = "system is NULL", NAO_ERR_INVALID_ARG);
+    nao_ctx c = s->ctx;
+    nao_status st = check_ctx(c);
+    if (st != NAO_OK) return st;
+    if ((st = check_prec(c, prec)) != NAO_OK) return st;
+    if (flags & ~NAO_TUNE_FORCE) return (set_err(c, "unknown flags"), NAO_ERR_INVALID_ARG);
+    const int64_t nb = s->basis.n_basis, np = s->n_points;
+    if ((np > 0 && !v) || (nb > 0 && !D)) return (set_err(c, "NULL v or D"), NAO_ERR_INVALID_ARG);
+    std::string key;
+    std::map<std::string, std::pair<int, int>> cache;
+    try {
+        key = tune_key(s, prec);
+        cache = tune_load();
+    } catch (...) {
+        return (set_err(c, "host allocation failed"), NAO_ERR_OUT_OF_MEMORY);
+    }
+    auto report = [&](int ht, int gm, double ms) {
+        if (h_tile_out) *h_tile_out = ht;
+        if (group_max_out) *group_max_out = gm;
+        if (best_ms) *best_ms = ms;
+    };
+    auto hit = cache.find(key);
+    if (!(flags & NAO_TUNE_FORCE) && hit != cache.end()) {
+        if ((st = tune_apply(s, hit->second.first, hit->second.second)) != NAO_OK) return st;
+        report(hit->second.first, hit->second.second, -1.0);
+        return NAO_OK;
+    }
+    // device-side inputs and outputs for the timing runs
+    DevArray dv, dD, dH, dn;
+    auto release = [&]() {
+        (void)hipStreamSynchronize(c->stream);
+        for (DevArray* a : {&dv, &dD, &dH, &dn}) dev_free(c, a->p, a->bytes);
+    };
+    const double* vin = v;
+    const double* Din = D;
+    if (space == NAO_MEM_HOST) {
+        if ((st = upload(c, dv, v, np * sizeof(double))) != NAO_OK) return release(), st;
+        if ((st = upload(c, dD, D, nb * nb * sizeof(double))) != NAO_OK) return release(), st;
+        vin = dv.as<double>();
+        Din = dD.as<double>();
+    }
+    if ((st = ensure(c, dH, std::max<int64_t>(1, nb * nb) * sizeof(double))) != NAO_OK) return release(), st;
+    if ((st = ensure(c, dn, std::max<int64_t>(1, np) * sizeof(double))) != NAO_OK) return release(), st;
+    std::vector<std::pair<int, int>> cand;
+    const bool dense = prec == NAO_FP64 || prec == NAO_FP32;
+    for (int gm : {256, 192, 128})
+        for (int ht : {64, 128})
+            if (dense || ht == 64) cand.push_back({ht, gm});
+    hipEvent_t e0 = take_event(c), e1 = take_event(c);
+    if (!e0 || !e1) return release(), (set_err(c, "event creation failed"), NAO_ERR_HIP);
+    const bool prof = c->prof;
+    c->prof = false;
+    double best = 1e300;
+    std::pair<int, int> pick = {s->h_tile, s->group_max};
+    for (const auto& cf : cand) {
+        if ((st = tune_apply(s, cf.first, cf.second)) != NAO_OK) break;
+        // one warm-up, then one timed density + Hamiltonian pair
+        if ((st = nao_update_density(s, Din, NAO_MEM_DEVICE, prec, dn.as<double>(), NAO_MEM_DEVICE, nullptr)) != NAO_OK ||
+            (st = nao_integrate_h(s, vin, NAO_MEM_DEVICE, prec, dH.as<double>(), NAO_MEM_DEVICE)) != NAO_OK)
+            break;
+        if (hipEventRecord(e0, c->stream) != hipSuccess) { st = NAO_ERR_HIP; break; }
+        if ((st = nao_update_density(s, Din, NAO_MEM_DEVICE, prec, dn.as<double>(), NAO_MEM_DEVICE, nullptr)) != NAO_OK ||
+            (st = nao_integrate_h(s, vin, NAO_MEM_DEVICE, prec, dH.as<double>(), NAO_MEM_DEVICE)) != NAO_OK)
+            break;
+        float ms = 0.0f;
+        if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            st = NAO_ERR_HIP;
+            break;
+        }
+        if (ms < best) {
+            best = ms;
+            pick = cf;
+        }
+    }
+    c->prof = prof;
+    c->pool.push_back(e0);
+    c->pool.push_back(e1);
+    release();
+    if (st == NAO_ERR_HIP) return hip_fail(c, hipGetLastError(), "autotune timing");
+    if (st != NAO_OK) return st;
+    if ((st = tune_apply(s, pick.first, pick.second)) != NAO_OK) return st;
+    try {
+        cache[key] = pick;
+        tune_save(cache);
+    } catch (...) {
+    }
+    report(pick.first, pick.second, best);
+    return NAO_OK;
+}

@@ -75,6 +75,7 @@ _sig("nao_build_batches", _S, _vp, ctypes.POINTER(BasisDesc), ctypes.c_int64, _c
      ctypes.POINTER(_vp))
 _sig("nao_system_set_group_max", _S, _vp, ctypes.c_int32)
 _sig("nao_system_set_h_tile", _S, _vp, ctypes.c_int32)
+_sig("nao_system_autotune", _S, _vp, ctypes.c_int, _vp, _vp, ctypes.c_int, ctypes.c_uint32, _c_i32p, _c_i32p, _c_dp)
 _sig("nao_system_info", _S, _vp, _c_i64p, _c_i64p, _c_i64p, ctypes.POINTER(ctypes.c_size_t))
 _sig("nao_get_batches", _S, _vp, _c_i64p, _c_i64p, _c_i64p, _c_i32p)
 _sig("nao_system_work", _S, _vp, _c_dp)
@@ -98,7 +99,7 @@ _sig("nao_server_destroy", None, _vp)
 EXPORTED = [
     "nao_ctx_create", "nao_ctx_destroy", "nao_last_error", "nao_ctx_set_stream", "nao_ctx_stream",
     "nao_ctx_synchronize", "nao_ctx_memory", "nao_ctx_profile", "nao_ctx_profile_read", "nao_plan_create", "nao_plan_info", "nao_plan_get_batches",
-    "nao_plan_destroy", "nao_build_batches", "nao_system_set_group_max", "nao_system_set_h_tile", "nao_system_info", "nao_get_batches",
+    "nao_plan_destroy", "nao_build_batches", "nao_system_set_group_max", "nao_system_set_h_tile", "nao_system_autotune", "nao_system_info", "nao_get_batches",
     "nao_system_work", "nao_eval_basis", "nao_integrate_h", "nao_update_density", "nao_system_destroy",
     "nao_run_many", "nao_server_create", "nao_server_open_session", "nao_server_close_session",
     "nao_server_session_info", "nao_server_submit", "nao_server_step", "nao_server_poll", "nao_server_result",
@@ -302,6 +303,17 @@ class System:
 
     def set_h_tile(self, t):
         _check(_lib.nao_system_set_h_tile(self.handle, int(t)), self.ctx.handle)
+
+    def autotune(self, v, D, precision="fp64", force=False):
+        """nao_system_autotune: returns (h_tile, group_max, best_ms or -1 if cached)."""
+        pv, sv, kv = _ptr_space(v)
+        pd, sd, kd = _ptr_space(D)
+        if sv != sd:
+            raise ValueError("v and D must be in the same memory space")
+        ht, gm, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        _check(_lib.nao_system_autotune(self.handle, PRECISIONS[precision], pv, pd, sv, 1 if force else 0,
+                                        ctypes.byref(ht), ctypes.byref(gm), ctypes.byref(ms)), self.ctx.handle)
+        return ht.value, gm.value, ms.value
 
     def work_units(self):
         u = ctypes.c_double()

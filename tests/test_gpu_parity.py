@@ -244,3 +244,23 @@ def test_wide_hamiltonian_tiles(nao, ctx, name, prec):
     else:
         assert rel_max(H128, H64) <= 1e-5 and rel_max(n128, n64) <= 1e-12
     s.close()
+
+
+def test_autotune_choice_and_cache(nao, ctx, tmp_path, monkeypatch):
+    """The autotuner keeps results exact, writes its cache, and a second system of the same
+    shape class takes the cached choice without timing."""
+    w, B, ref = case("multitile")
+    say("autotune")
+    monkeypatch.setenv("NAO_TUNE_CACHE", str(tmp_path / "tune.json"))
+    s = nao.build_batches(ctx, w["basis"], w["xyz"], w["w"], w["max_batch"])
+    ht, gm, ms = s.autotune(w["v"], w["D"], precision="fp64", force=True)
+    assert ht in (64, 128) and gm in (128, 192, 256) and ms > 0
+    assert rel_max(s.integrate_h(w["v"]), ref["H"]) <= TOL
+    assert rel_max(s.update_density(w["D"]), ref["n"]) <= TOL
+    text = (tmp_path / "tune.json").read_text()
+    assert "fp64" in text and str(ht) in text
+    s2 = nao.build_batches(ctx, w["basis"], w["xyz"], w["w"], w["max_batch"])
+    ht2, gm2, ms2 = s2.autotune(w["v"], w["D"], precision="fp64")
+    assert (ht2, gm2, ms2) == (ht, gm, -1.0)
+    s.close()
+    s2.close()
