@@ -258,25 +258,39 @@ nao_status nao_run_many(nao_ctx ctx, const nao_work* work, int64_t n_work, nao_p
  * sessions, and packs the oldest ready requests (at most one per session in flight, up to
  * max_per_launch per launch) into each free slot as one nao_run_many launch, so requests that
  * arrive while others run join the next launch on a free slot and overlap on the device.
+ * Admission (planning and upload of a session's system) runs on a builder thread of the
+ * server, so it never stalls the dispatch of resident sessions; a session whose setup fails
+ * for another reason than the budget fails its requests (NAO_REQ_FAILED).  The home context
+ * belongs to the server while it exists.
  * Inputs D and v stay owned by the caller and must stay valid until the request is done.
  * Times are seconds since the server was created (host steady clock).
  * ------------------------------------------------------------------------------------- */
 typedef struct nao_server_s* nao_server;
 
-typedef enum { NAO_REQ_WAITING = 0, NAO_REQ_RUNNING = 1, NAO_REQ_DONE = 2 } nao_request_state;
+typedef enum { NAO_REQ_WAITING = 0, NAO_REQ_RUNNING = 1, NAO_REQ_DONE = 2, NAO_REQ_FAILED = 3 } nao_request_state;
 
 /* group_max: execution-group size of the sessions' systems (as nao_system_set_group_max;
  * 0 = every octree batch its own unit). */
 nao_status nao_server_create(nao_ctx home, int32_t n_slots, int32_t max_per_launch, int32_t group_max,
                              nao_precision precision, nao_server* out);
-/* Queue a structure (copied); returns its session id.  Admission happens in nao_server_step. */
+/* Queue a structure (copied); returns its session id.  The server's builder thread admits
+ * queued sessions in open order as the budget allows. */
 nao_status nao_server_open_session(nao_server srv, const nao_basis_desc* basis, int64_t n_points,
                                    const double* point_xyz, const double* point_w, int32_t max_batch,
                                    int64_t* session);
 /* The session's resources are released once its last request is done. */
 nao_status nao_server_close_session(nao_server srv, int64_t session);
-/* resident: 1 once admitted; bytes: its device footprint (0 before admission). */
-nao_status nao_server_session_info(nao_server srv, int64_t session, int32_t* resident, size_t* bytes,
+typedef enum {
+    NAO_SESSION_QUEUED = 0,      /* waiting for (or in) admission */
+    NAO_SESSION_RESIDENT = 1,    /* admitted: its requests can run */
+    NAO_SESSION_NO_MEMORY = 2,   /* its last admission attempt did not fit the budget; retried
+                                    after another session is released */
+    NAO_SESSION_CLOSED = 3,      /* released */
+    NAO_SESSION_FAILED = 4       /* admission failed for another reason (see nao_last_error of
+                                    the home context) */
+} nao_session_state;
+/* state: a nao_session_state; bytes: its device footprint (0 unless resident). */
+nao_status nao_server_session_info(nao_server srv, int64_t session, int32_t* state, size_t* bytes,
                                    int64_t* n_basis, int64_t* n_points);
 nao_status nao_server_submit(nao_server srv, int64_t session, const double* D, nao_memspace D_space,
                              const double* v, nao_memspace v_space, uint64_t* ticket);

@@ -7,6 +7,7 @@
 #include <cstring>
 #include <fstream>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -43,6 +44,7 @@ struct nao_ctx_s {
     size_t budget = 0;
     size_t used = 0;
     bool failed = false;
+    std::mutex err_mu;           // err may be set from a server's builder thread
     std::string err;
     double* scratch = nullptr;   // basis values of one block of units
     size_t scratch_elems = 0;
@@ -68,7 +70,10 @@ namespace {
 
 void set_err(nao_ctx c, const std::string& m)
 {
-    if (c) c->err = m;
+    if (c) {
+        std::lock_guard<std::mutex> lk(c->err_mu);
+        c->err = m;
+    }
     g_thread_error = m;
 }
 
@@ -181,7 +186,12 @@ nao_status check_ctx(nao_ctx c)
         return NAO_ERR_INVALID_ARG;
     }
     if (c->failed) {
-        set_err(c, "context is unusable after an earlier HIP failure: " + c->err);
+        std::string first;
+        {
+            std::lock_guard<std::mutex> lk(c->err_mu);
+            first = c->err;
+        }
+        set_err(c, "context is unusable after an earlier HIP failure: " + first);
         return NAO_ERR_HIP;
     }
     hipError_t e = hipSetDevice(c->device);
@@ -771,8 +781,11 @@ void nao_ctx_destroy(nao_ctx c)
 
 const char* nao_last_error(nao_ctx c)
 {
-    if (c) return c->err.c_str();
-    return g_thread_error.c_str();
+    if (!c) return g_thread_error.c_str();
+    static thread_local std::string copy;  // the caller's view stays valid until its next call
+    std::lock_guard<std::mutex> lk(c->err_mu);
+    copy = c->err;
+    return copy.c_str();
 }
 
 nao_status nao_ctx_set_stream(nao_ctx c, void* hip_stream)

@@ -3,11 +3,14 @@
 // nao_run_many.  Host-side only; every GPU step is a library call on a slot's stream.
 #include <algorithm>
 #include <chrono>
+#include <condition_variable>
 #include <cstring>
 #include <deque>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
@@ -54,7 +57,9 @@ struct HostStructure {
     }
 };
 
-enum SessionState { S_PENDING, S_RESIDENT, S_GONE };
+// PENDING -> BUILDING -> RESIDENT -> RELEASING -> GONE; the builder thread owns BUILDING and
+// RELEASING (it alone uses the home context), the scheduler dispatches RESIDENT sessions.
+enum SessionState { S_PENDING, S_BUILDING, S_RESIDENT, S_RELEASING, S_GONE };
 
 struct Session {
     SessionState state = S_PENDING;
@@ -62,10 +67,12 @@ struct Session {
     nao_system sys = nullptr;
     int64_t n_basis = 0, n_points = 0;
     double *D = nullptr, *v = nullptr, *H = nullptr, *n = nullptr;
-    size_t buf_bytes = 0, bytes = 0;
+    size_t bytes = 0;
     bool close_requested = false;
     bool busy = false;        // a request of this session is running
     bool have_v = false;
+    bool no_memory = false;   // the last admission attempt did not fit the budget
+    bool failed = false;      // admission failed for another reason
 };
 
 struct Request {
@@ -89,6 +96,11 @@ struct Slot {
 }  // namespace
 
 struct nao_server_s {
+    std::mutex mu;                      // sessions, queues, requests
+    std::condition_variable cv;         // wakes the builder
+    std::thread builder;
+    bool stop = false;
+    uint64_t releases = 0;              // sessions released so far (budget waits on it)
     nao_ctx home = nullptr;
     nao_precision prec = NAO_FP64;
     int32_t max_per_launch = 8;
@@ -116,20 +128,23 @@ nao_status fail(nao_server s, nao_status st, const std::string& m)
     return st;
 }
 
+size_t matrix_bytes(int64_t nb) { return (size_t)std::max<int64_t>(1, nb * nb) * sizeof(double); }
+size_t points_bytes(int64_t np) { return (size_t)std::max<int64_t>(1, np) * sizeof(double); }
+
+// Builder thread only: frees a session's system and buffers through the home context.
 void release_session(nao_server srv, Session& se)
 {
     if (se.sys) nao_system_destroy(se.sys);
     se.sys = nullptr;
-    ctx_free(srv->home, se.D, se.n_basis * se.n_basis * sizeof(double));
-    ctx_free(srv->home, se.H, se.n_basis * se.n_basis * sizeof(double));
-    ctx_free(srv->home, se.v, se.n_points * sizeof(double));
-    ctx_free(srv->home, se.n, se.n_points * sizeof(double));
+    ctx_free(srv->home, se.D, matrix_bytes(se.n_basis));
+    ctx_free(srv->home, se.H, matrix_bytes(se.n_basis));
+    ctx_free(srv->home, se.v, points_bytes(se.n_points));
+    ctx_free(srv->home, se.n, points_bytes(se.n_points));
     se.D = se.H = se.v = se.n = nullptr;
-    se.state = S_GONE;
     se.bytes = 0;
 }
 
-// Try to make a pending session resident; NAO_ERR_BUDGET means "not now".
+// Builder thread only: makes a session resident; NAO_ERR_BUDGET means "not now".
 nao_status admit(nao_server srv, Session& se)
 {
     nao_system sys = nullptr;
@@ -143,8 +158,7 @@ nao_status admit(nao_server srv, Session& se)
     int64_t nb = 0, np = (int64_t)se.host.w.size();
     nao_system_info(sys, &nb, nullptr, nullptr, nullptr);
     void *D = nullptr, *H = nullptr, *v = nullptr, *n = nullptr;
-    const size_t mb = (size_t)std::max<int64_t>(1, nb * nb) * sizeof(double);
-    const size_t pb = (size_t)std::max<int64_t>(1, np) * sizeof(double);
+    const size_t mb = matrix_bytes(nb), pb = points_bytes(np);
     if ((st = ctx_alloc(srv->home, mb, &D)) == NAO_OK && (st = ctx_alloc(srv->home, mb, &H)) == NAO_OK &&
         (st = ctx_alloc(srv->home, pb, &v)) == NAO_OK && (st = ctx_alloc(srv->home, pb, &n)) == NAO_OK) {
         se.sys = sys;
@@ -155,8 +169,6 @@ nao_status admit(nao_server srv, Session& se)
         se.v = static_cast<double*>(v);
         se.n = static_cast<double*>(n);
         se.bytes = system_device_bytes(sys) + 2 * mb + 2 * pb;
-        se.state = S_RESIDENT;
-        // the host copy is no longer needed
         se.host.xyz.clear();
         se.host.xyz.shrink_to_fit();
         se.host.w.clear();
@@ -171,8 +183,86 @@ nao_status admit(nao_server srv, Session& se)
     return st;
 }
 
+bool queued_for(nao_server srv, int64_t sid)
+{
+    for (uint64_t tk : srv->ready)
+        if (srv->reqs[tk].session == sid) return true;
+    return false;
+}
+
+// The builder: releases closed sessions and admits pending ones in open order, off the
+// scheduler's path.  A session that does not fit waits (and blocks those behind it) until
+// another one has been released.
+void builder_loop(nao_server srv)
+{
+    std::unique_lock<std::mutex> lk(srv->mu);
+    uint64_t seen_releases = srv->releases;
+    bool blocked = false;
+    for (;;) {
+        srv->cv.wait(lk, [&] {
+            if (srv->stop) return true;
+            for (auto& kv : srv->sessions)
+                if (kv.second.state == S_RELEASING) return true;
+            return !srv->pending.empty() && (!blocked || srv->releases != seen_releases);
+        });
+        if (srv->stop) return;
+        // releases first: they make room
+        for (auto& kv : srv->sessions) {
+            Session& se = kv.second;
+            if (se.state != S_RELEASING) continue;
+            lk.unlock();
+            release_session(srv, se);
+            lk.lock();
+            se.state = S_GONE;
+            ++srv->releases;
+        }
+        while (!srv->pending.empty()) {
+            const int64_t id = srv->pending.front();
+            Session& se = srv->sessions[id];
+            if (se.state != S_PENDING) {
+                srv->pending.pop_front();
+                continue;
+            }
+            se.state = S_BUILDING;
+            lk.unlock();
+            const nao_status st = admit(srv, se);
+            lk.lock();
+            if (st == NAO_OK) {
+                se.state = S_RESIDENT;
+                se.no_memory = false;
+                srv->pending.pop_front();
+                blocked = false;
+                continue;
+            }
+            bool others = false;  // resident sessions whose release could make room
+            for (auto& kv : srv->sessions)
+                others = others || (kv.first != id && (kv.second.state == S_RESIDENT || kv.second.state == S_RELEASING));
+            if (st == NAO_ERR_BUDGET && others) {
+                se.state = S_PENDING;
+                se.no_memory = true;
+                blocked = true;
+                seen_releases = srv->releases;
+                break;
+            }
+            if (st == NAO_ERR_BUDGET) ctx_set_error(srv->home, "session does not fit the budget of the home context");
+            // any other failure (or a session larger than the whole budget): it and its requests fail
+            se.state = S_GONE;
+            se.failed = true;
+            srv->pending.pop_front();
+            for (auto& kv : srv->reqs)
+                if (kv.second.session == id && kv.second.state == NAO_REQ_WAITING) kv.second.state = NAO_REQ_FAILED;
+            std::deque<uint64_t> keep;
+            for (uint64_t tk : srv->ready)
+                if (srv->reqs[tk].session != id) keep.push_back(tk);
+            srv->ready.swap(keep);
+        }
+    }
+}
+
+// Scheduler side (caller holds mu): finished launches, then sessions that can be released.
 nao_status retire(nao_server srv)
 {
+    bool released = false;
     for (Slot& sl : srv->slots) {
         if (!sl.busy) continue;
         const hipError_t e = hipEventQuery(sl.done);
@@ -183,22 +273,20 @@ nao_status retire(nao_server srv)
             Request& r = srv->reqs[tk];
             r.state = NAO_REQ_DONE;
             r.t_end = t;
-            Session& se = srv->sessions[r.session];
-            se.busy = false;
+            srv->sessions[r.session].busy = false;
         }
         sl.tickets.clear();
         sl.busy = false;
-        nao_ctx_synchronize(sl.ctx);  // frees the finished launch plan
+        nao_ctx_synchronize(sl.ctx);  // frees the finished launch plan of this slot
     }
-    // sessions whose last request is done and that were closed
     for (auto& kv : srv->sessions) {
         Session& se = kv.second;
-        if (se.close_requested && !se.busy && se.state == S_RESIDENT) {
-            bool queued = false;
-            for (uint64_t tk : srv->ready) queued = queued || srv->reqs[tk].session == kv.first;
-            if (!queued) release_session(srv, se);
+        if (se.close_requested && !se.busy && se.state == S_RESIDENT && !queued_for(srv, kv.first)) {
+            se.state = S_RELEASING;
+            released = true;
         }
     }
+    if (released) srv->cv.notify_all();
     return NAO_OK;
 }
 
@@ -283,6 +371,12 @@ nao_status nao_server_create(nao_ctx home, int32_t n_slots, int32_t max_per_laun
             return st;
         }
     }
+    try {
+        srv->builder = std::thread(builder_loop, srv);
+    } catch (...) {
+        nao_server_destroy(srv);
+        return NAO_ERR_INTERNAL;
+    }
     *out = srv;
     return NAO_OK;
 }
@@ -294,42 +388,59 @@ nao_status nao_server_open_session(nao_server srv, const nao_basis_desc* basis, 
         return NAO_ERR_INVALID_ARG;
     if (!basis->species_shell_ptr || basis->n_species < 1) return fail(srv, NAO_ERR_INVALID_ARG, "bad basis");
     try {
+        HostStructure host;
+        host.take(basis, n_points, point_xyz, point_w, max_batch);
+        std::lock_guard<std::mutex> lk(srv->mu);
         const int64_t id = srv->next_session++;
         Session& se = srv->sessions[id];
-        se.host.take(basis, n_points, point_xyz, point_w, max_batch);
+        se.host = std::move(host);
+        se.host.desc.atom_xyz = se.host.atom_xyz.data();  // re-point the copy after the move
+        se.host.desc.atom_species = se.host.atom_species.data();
+        se.host.desc.species_shell_ptr = se.host.shell_ptr.data();
+        se.host.desc.shell_l = se.host.shell_l.data();
+        se.host.desc.shell_radial = se.host.shell_radial.data();
+        se.host.desc.radial_rmin = se.host.rmin.data();
+        se.host.desc.radial_rcut = se.host.rcut.data();
+        se.host.desc.radial_samples = se.host.samples.data();
         se.n_points = n_points;
         srv->pending.push_back(id);
         *session = id;
-        return NAO_OK;
     } catch (const std::bad_alloc&) {
         return fail(srv, NAO_ERR_OUT_OF_MEMORY, "host allocation failed");
     }
+    srv->cv.notify_all();
+    return NAO_OK;
 }
 
 nao_status nao_server_close_session(nao_server srv, int64_t session)
 {
     if (!srv) return NAO_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(srv->mu);
     auto it = srv->sessions.find(session);
-    if (it == srv->sessions.end() || it->second.state == S_GONE) return fail(srv, NAO_ERR_INVALID_ARG, "unknown session");
+    if (it == srv->sessions.end() || it->second.state == S_GONE || it->second.close_requested)
+        return fail(srv, NAO_ERR_INVALID_ARG, "unknown or closed session");
     it->second.close_requested = true;
-    if (it->second.state == S_PENDING) {
-        bool queued = false;
-        for (uint64_t tk : srv->ready) queued = queued || srv->reqs[tk].session == session;
-        if (!queued) {
-            srv->pending.erase(std::remove(srv->pending.begin(), srv->pending.end(), session), srv->pending.end());
-            it->second.state = S_GONE;
-        }
+    if (it->second.state == S_PENDING && !queued_for(srv, session)) {
+        srv->pending.erase(std::remove(srv->pending.begin(), srv->pending.end(), session), srv->pending.end());
+        it->second.state = S_GONE;
     }
     return NAO_OK;
 }
 
-nao_status nao_server_session_info(nao_server srv, int64_t session, int32_t* resident, size_t* bytes, int64_t* n_basis,
+nao_status nao_server_session_info(nao_server srv, int64_t session, int32_t* state, size_t* bytes, int64_t* n_basis,
                                    int64_t* n_points)
 {
     if (!srv) return NAO_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(srv->mu);
     auto it = srv->sessions.find(session);
     if (it == srv->sessions.end()) return fail(srv, NAO_ERR_INVALID_ARG, "unknown session");
-    if (resident) *resident = it->second.state == S_RESIDENT;
+    const Session& se = it->second;
+    if (state) {
+        if (se.state == S_RESIDENT) *state = NAO_SESSION_RESIDENT;
+        else if (se.failed) *state = NAO_SESSION_FAILED;
+        else if (se.state == S_GONE || se.state == S_RELEASING) *state = NAO_SESSION_CLOSED;
+        else *state = se.no_memory ? NAO_SESSION_NO_MEMORY : NAO_SESSION_QUEUED;
+    }
     if (bytes) *bytes = it->second.bytes;
     if (n_basis) *n_basis = it->second.n_basis;
     if (n_points) *n_points = it->second.n_points;
@@ -340,6 +451,7 @@ nao_status nao_server_submit(nao_server srv, int64_t session, const double* D, n
                              nao_memspace v_space, uint64_t* ticket)
 {
     if (!srv || !ticket) return NAO_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(srv->mu);
     auto it = srv->sessions.find(session);
     if (it == srv->sessions.end() || it->second.state == S_GONE || it->second.close_requested)
         return fail(srv, NAO_ERR_INVALID_ARG, "unknown or closed session");
@@ -366,20 +478,9 @@ nao_status nao_server_submit(nao_server srv, int64_t session, const double* D, n
 nao_status nao_server_step(nao_server srv, int32_t* n_running, int32_t* n_waiting)
 {
     if (!srv) return NAO_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(srv->mu);
     nao_status st = retire(srv);
     if (st != NAO_OK) return st;
-    // admission in open order; the first session that does not fit blocks the ones behind it
-    while (!srv->pending.empty()) {
-        Session& se = srv->sessions[srv->pending.front()];
-        if (se.state != S_PENDING) {
-            srv->pending.pop_front();
-            continue;
-        }
-        st = admit(srv, se);
-        if (st == NAO_ERR_BUDGET) break;
-        if (st != NAO_OK) return st;
-        srv->pending.pop_front();
-    }
     for (Slot& sl : srv->slots)
         if (!sl.busy && (st = dispatch(srv, sl)) != NAO_OK) return st;
     int32_t run = 0, wait = (int32_t)srv->ready.size();
@@ -393,6 +494,7 @@ nao_status nao_server_poll(nao_server srv, uint64_t ticket, int32_t* state, doub
                            double* t_end)
 {
     if (!srv) return NAO_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(srv->mu);
     auto it = srv->reqs.find(ticket);
     if (it == srv->reqs.end()) return fail(srv, NAO_ERR_INVALID_ARG, "unknown ticket");
     if (state) *state = it->second.state;
@@ -405,6 +507,7 @@ nao_status nao_server_poll(nao_server srv, uint64_t ticket, int32_t* state, doub
 nao_status nao_server_result(nao_server srv, uint64_t ticket, double* H, double* n, nao_memspace space)
 {
     if (!srv) return NAO_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(srv->mu);
     auto it = srv->reqs.find(ticket);
     if (it == srv->reqs.end() || it->second.state != NAO_REQ_DONE) return fail(srv, NAO_ERR_NOT_READY, "request not done");
     Session& se = srv->sessions[it->second.session];
@@ -420,11 +523,16 @@ nao_status nao_server_result(nao_server srv, uint64_t ticket, double* H, double*
 void nao_server_destroy(nao_server srv)
 {
     if (!srv) return;
-    for (Slot& sl : srv->slots) {
-        if (sl.ctx) nao_ctx_synchronize(sl.ctx);
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->stop = true;
     }
+    srv->cv.notify_all();
+    if (srv->builder.joinable()) srv->builder.join();
+    for (Slot& sl : srv->slots)
+        if (sl.ctx) nao_ctx_synchronize(sl.ctx);
     for (auto& kv : srv->sessions)
-        if (kv.second.state == S_RESIDENT) release_session(srv, kv.second);
+        if (kv.second.state == S_RESIDENT || kv.second.state == S_RELEASING) release_session(srv, kv.second);
     for (Slot& sl : srv->slots) {
         if (sl.done) (void)hipEventDestroy(sl.done);
         if (sl.ctx) nao_ctx_destroy(sl.ctx);

@@ -10,6 +10,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import time
 import weakref
 
 import numpy as np
@@ -211,6 +212,10 @@ class Context:
         except Exception:
             pass
 
+    def last_error(self):
+        msg = _lib.nao_last_error(self.handle)
+        return msg.decode() if msg else ""
+
     def synchronize(self):
         _check(_lib.nao_ctx_synchronize(self.handle), self.handle)
 
@@ -367,7 +372,8 @@ class System:
 # ---------------------------------------------------------------------------------------------
 # serving core
 
-REQ_WAITING, REQ_RUNNING, REQ_DONE = 0, 1, 2
+REQ_WAITING, REQ_RUNNING, REQ_DONE, REQ_FAILED = 0, 1, 2, 3
+SESSION_QUEUED, SESSION_RESIDENT, SESSION_NO_MEMORY, SESSION_CLOSED, SESSION_FAILED = 0, 1, 2, 3, 4
 
 
 class Server:
@@ -411,7 +417,20 @@ class Server:
         r, b, nb, npt = ctypes.c_int32(), ctypes.c_size_t(), ctypes.c_int64(), ctypes.c_int64()
         _check(_lib.nao_server_session_info(self.handle, int(sid), ctypes.byref(r), ctypes.byref(b), ctypes.byref(nb),
                                             ctypes.byref(npt)), self.home.handle)
-        return dict(resident=bool(r.value), bytes=b.value, n_basis=nb.value, n_points=npt.value)
+        return dict(state=r.value, resident=r.value == SESSION_RESIDENT, bytes=b.value, n_basis=nb.value,
+                    n_points=npt.value)
+
+    def wait_settled(self, sid, timeout=60.0):
+        """Step the server until the session is resident, out of memory, closed or failed."""
+        t0 = time.monotonic()
+        while True:
+            self.step()
+            info = self.session_info(sid)
+            if info["state"] != SESSION_QUEUED:
+                return info
+            if time.monotonic() - t0 > timeout:
+                raise TimeoutError("session %d not admitted within %.0f s" % (sid, timeout))
+            time.sleep(0.0005)
 
     def submit(self, sid, D, v=None):
         """Queue one iteration; D (and v) must stay valid until the request is done."""
@@ -435,7 +454,7 @@ class Server:
         a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
         _check(_lib.nao_server_poll(self.handle, int(ticket), ctypes.byref(st), ctypes.byref(a), ctypes.byref(b),
                                     ctypes.byref(c)), self.home.handle)
-        if st.value == REQ_DONE:
+        if st.value in (REQ_DONE, REQ_FAILED):
             self._keep.pop(int(ticket), None)
         return st.value, a.value, b.value, c.value
 

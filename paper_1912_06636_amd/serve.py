@@ -4,9 +4,10 @@ Requests are SCF-iteration pairs (density update from a fresh density matrix, th
 Hamiltonian with the structure's potential) for structures of 20-400 atoms shaped like the
 100-atom block or the 375-atom slab.  Sessions keep a structure resident for 10-40
 iterations; a request joins the oldest session with no request in flight, otherwise it opens
-a new session.  The structures come from a pool generated before the run; each iteration's
-density matrix D = C C^T (C seeded per session and iteration) is staged on the device before
-the request is submitted, and its staging time is reported separately.
+a new session.  The structures come from a pool generated before the run.  A session's
+density matrix D = C C^T (C seeded per session) and potential are staged on the device when
+it opens (that staging time is reported separately); every request of the session stages
+that D into the session's buffer and runs both operations in full.
 
 Two paths are compared:
   * plain:   FP64, one request per launch, one slot, every octree batch its own unit;
@@ -51,6 +52,14 @@ class DensityStager:
         self.torch = torch
         self.device = device
         self.masks = {}
+        # a stream of its own, so that waiting for a staged input never waits for the server
+        self.stream = torch.cuda.Stream(device=device)
+
+    def upload(self, a):
+        with self.torch.cuda.stream(self.stream):
+            t = self.torch.from_numpy(a).to(self.device, non_blocking=False)
+        self.stream.synchronize()
+        return t
 
     def make(self, work, session_seed, iteration):
         torch = self.torch
@@ -60,14 +69,17 @@ class DensityStager:
             xyz = work["basis"]["atom_xyz"]
             dd = np.sqrt(((xyz[:, None] - xyz[None]) ** 2).sum(-1))
             keep = (dd <= work["d_max"])[ba][:, ba]
-            self.masks[key] = torch.from_numpy(keep).to(self.device)
+            self.masks[key] = self.upload(keep)
         gen = torch.Generator(device=self.device)
         gen.manual_seed(int(session_seed) * 100003 + int(iteration))
-        C = torch.randn((work["n_basis"], work["n_occ"]), generator=gen, dtype=torch.float64, device=self.device)
-        D = C @ C.T
-        D = 0.5 * (D + D.T)
-        D.mul_(self.masks[key])
-        return D.contiguous()
+        with torch.cuda.stream(self.stream):
+            C = torch.randn((work["n_basis"], work["n_occ"]), generator=gen, dtype=torch.float64, device=self.device)
+            D = C @ C.T
+            D = 0.5 * (D + D.T)
+            D.mul_(self.masks[key])
+            D = D.contiguous()
+        self.stream.synchronize()
+        return D
 
 
 def run(nao, torch, pool, lam, duration_s, max_requests, path, precision="bf16x3", n_slots=3,
@@ -103,15 +115,14 @@ def run(nao, torch, pool, lam, duration_s, max_requests, path, precision="bf16x3
                 s = dict(sid=sid, work=w, k=0, K=int(rng.integers(10, 41)), busy=False, opened=now,
                          seed=len(sessions) + 1)
                 sessions.append(s)
-            ts = time.perf_counter()
-            D = stager.make(s["work"], s["seed"], s["k"])
-            torch.cuda.synchronize()
-            stage_s += time.perf_counter() - ts
             v = None
             if s["k"] == 0:
-                v = torch.from_numpy(s["work"]["v"]).to(dev)
-                torch.cuda.synchronize()
+                ts = time.perf_counter()
+                s["D"] = stager.make(s["work"], s["seed"], 0)
+                v = stager.upload(s["work"]["v"])
                 vbuf[s["sid"]] = v
+                stage_s += time.perf_counter() - ts
+            D = s["D"]
             tk = srv.submit(s["sid"], D, v)
             tickets[tk] = (s, D)
             s["busy"] = True
@@ -121,6 +132,8 @@ def run(nao, torch, pool, lam, duration_s, max_requests, path, precision="bf16x3
         srv.step()
         for tk in list(tickets):
             st, t_sub, t_start, t_end = srv.poll(tk)
+            if st == nao.REQ_FAILED:
+                raise RuntimeError("request %d failed: %s" % (tk, home.last_error()))
             if st == nao.REQ_DONE:
                 s, _ = tickets.pop(tk)
                 s["busy"] = False
@@ -130,15 +143,16 @@ def run(nao, torch, pool, lam, duration_s, max_requests, path, precision="bf16x3
                 if s["k"] >= s["K"]:
                     srv.close_session(s["sid"])
                     vbuf.pop(s["sid"], None)
+                    s.pop("D", None)
         time.sleep(0.0002)
     elapsed = time.perf_counter() - t0
-    # drain what is still running so that the context can be torn down
+    # requests still waiting are dropped with the server; wait only for the running ones
+    backlog = sum(1 for tk in tickets if srv.poll(tk)[0] == nao.REQ_WAITING)
     t_drain = time.perf_counter()
-    while tickets and time.perf_counter() - t_drain < 120:
-        srv.step()
-        for tk in list(tickets):
-            if srv.poll(tk)[0] == nao.REQ_DONE:
-                tickets.pop(tk)
+    while time.perf_counter() - t_drain < 120:
+        running, _ = srv.step()
+        if running == 0:
+            break
         time.sleep(0.001)
     srv.close()
     home.close()
@@ -149,7 +163,7 @@ def run(nao, torch, pool, lam, duration_s, max_requests, path, precision="bf16x3
                gpt_basis2_per_s=round(2.0 * units_done / elapsed / 1e9, 3),
                p50_ms=round(float(np.percentile(lat, 50)), 2) if len(lat) else None,
                p99_ms=round(float(np.percentile(lat, 99)), 2) if len(lat) else None,
-               staging_s=round(stage_s, 2), sessions=len(sessions))
+               staging_s=round(stage_s, 2), sessions=len(sessions), backlog_at_end=int(backlog))
     if log:
         log("serve %s" % out)
     return out

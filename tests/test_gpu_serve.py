@@ -88,8 +88,7 @@ def test_admission_by_budget_and_iterations(lib):
     probe = lib.Context(0)
     s0 = lib.Server(probe, n_slots=1, max_per_launch=1)
     sid = s0.open_session(works[0]["basis"], works[0]["xyz"], works[0]["w"], 256)
-    s0.step()
-    one = s0.session_info(sid)["bytes"]
+    one = s0.wait_settled(sid)["bytes"]
     used_before, _ = probe.memory()
     s0.close()
     probe.close()
@@ -98,9 +97,9 @@ def test_admission_by_budget_and_iterations(lib):
     home = lib.Context(0, hbm_budget=int(used_before + one // 2))
     srv = lib.Server(home, n_slots=2, max_per_launch=4)
     sids = [srv.open_session(w["basis"], w["xyz"], w["w"], 256) for w in works]
-    srv.step()
-    resident = [srv.session_info(s)["resident"] for s in sids]
-    assert resident[0] and not resident[1] and not resident[2]
+    assert srv.wait_settled(sids[0])["state"] == lib.SESSION_RESIDENT
+    assert srv.wait_settled(sids[1])["state"] == lib.SESSION_NO_MEMORY
+    assert srv.session_info(sids[2])["state"] in (lib.SESSION_QUEUED, lib.SESSION_NO_MEMORY)  # behind sids[1]
     # two iterations on the first session, then close it: the next one gets admitted
     t1 = srv.submit(sids[0], works[0]["D"], works[0]["v"])
     t2 = srv.submit(sids[0], works[0]["D"])          # keeps the previous v
@@ -112,6 +111,7 @@ def test_admission_by_budget_and_iterations(lib):
     srv.close_session(sids[0])
     drain(srv, [t3])
     assert srv.session_info(sids[1])["resident"]
+    assert srv.session_info(sids[0])["state"] == lib.SESSION_CLOSED
     H = np.empty((works[1]["n_basis"],) * 2)
     srv.result(t3, H)
     other = lib.Context(0)                            # the home context has no room left
@@ -119,5 +119,22 @@ def test_admission_by_budget_and_iterations(lib):
     assert rel_max(H, sysm.integrate_h(works[1]["v"])) <= 1e-12
     sysm.close()
     other.close()
+    srv.close()
+    home.close()
+
+
+def test_session_larger_than_budget_fails(lib):
+    say("serve oversize session")
+    w = small(20, 12)
+    home = lib.Context(0, hbm_budget=1 << 20)
+    srv = lib.Server(home, n_slots=1, max_per_launch=1)
+    sid = srv.open_session(w["basis"], w["xyz"], w["w"], 256)
+    try:
+        tk = srv.submit(sid, w["D"], w["v"])
+    except lib.NaoError:
+        tk = None                                     # the builder was quicker: already failed
+    assert srv.wait_settled(sid)["state"] == lib.SESSION_FAILED
+    if tk is not None:
+        assert srv.poll(tk)[0] == lib.REQ_FAILED
     srv.close()
     home.close()
