@@ -27,7 +27,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "H-integration + density-update Gpt·basis²/s vs plain FP64; p50/p99 latency"
-PEAK = {"fp64": 78.6, "fp32": 157.3}  # TFLOP/s, dense MFMA, MI355X
+PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0, "bf16x6": 2500.0}  # TFLOP/s, dense MFMA, MI355X
+KERNELS_SRC = os.path.join(ROOT, "paper_1912_06636_amd", "csrc", "kernels.hip")
+# HBM bytes per launch of the contraction kernels on the default workload, from two rocprofv3
+# --pmc passes (FETCH_SIZE, WRITE_SIZE) over "bench.py --steps 1 --warmup 0 --h-tile 64
+# --no-cpu-baseline --calibrate-copy 1024", each counter scaled by its reading of the 1 GiB
+# plain copy made in that run.  Valid only for the kernel source it was taken on (sha256).
+TRAFFIC = {"sha256": "43b7903e16be0f550b24de811485febd8b6dc54671a12f4d9b51332212aaf17e",
+           "workload": "slab375", "precision": "fp64", "h_tile": 64, "group_max": 256,
+           "bytes_per_launch": {"n_f64": 5.970e9, "h_f64": 6.019e9}}
 WORKLOADS = {
     "slab375": (4, "375-atom layered slab, 28 NAO/atom (10,500 basis functions, l<=3, 6 A cutoff), "
                    "60x434 grid/atom = 9,765,000 points, octree batches <= 256"),
@@ -39,6 +47,19 @@ WORKLOADS = {
                   "lattice, 14 NAO/atom, 50x302 grid/atom, octree batches <= 256, all in one "
                   "hipGraph-captured launch sequence (nao_run_many)"),
 }
+
+
+def measured_traffic(workload, prec, h_tile, group_max, kernel):
+    """Counter-derived HBM bytes per launch of `kernel`, or None when the kernel source or the
+    launch configuration differ from the ones the counters were taken on."""
+    import hashlib
+    with open(KERNELS_SRC, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    t = TRAFFIC
+    if (t["sha256"] != sha or t["workload"] != workload or t["precision"] != prec or t["h_tile"] != h_tile
+            or t["group_max"] != group_max):
+        return None
+    return t["bytes_per_launch"].get(kernel)
 
 
 def log(*a):
@@ -68,7 +89,7 @@ def cpu_baseline(work, perm, bp, lp, li, budget_s):
     sizes = np.diff(bp)
     ms = np.diff(lp)
     live = np.nonzero(ms > 0)[0]
-    # grow the sample until one pass takes about budget_s / 2 per operation
+    # double the sample until one pass (both operations) takes about budget_s / 2
     stride = max(1, len(live) // 64)
     done_units, done_t, used = 0.0, 0.0, 0
     while True:
@@ -84,7 +105,7 @@ def cpu_baseline(work, perm, bp, lp, li, budget_s):
         units = float(np.sum(sizes[sel].astype(np.float64) * ms[sel].astype(np.float64) ** 2))
         done_units, done_t = units, t
         used += 1
-        if t >= budget_s / 4 or len(sel) >= len(live) or used > 6:
+        if t >= budget_s / 2 or len(sel) >= len(live) or used > 7:
             break
         stride = max(1, stride // 2)
     rate = 2.0 * done_units / done_t / 1e9
@@ -214,10 +235,12 @@ def main():
         n = torch.empty(sysm.n_points, dtype=torch.float64, device=dev)
     torch.cuda.synchronize()
     tuned = None
+    h_tile_used, group_max_used = args.h_tile or 64, args.group_max
     if not args.h_tile:
         t0 = time.time()
         ht, gm, ms = sysm.autotune(v, D, precision=args.precision, force=True)
         tuned = {"h_tile": ht, "group_max": gm, "best_ms": round(ms, 3)}
+        h_tile_used, group_max_used = ht, gm
         log("autotuned in %.1f s: %s" % (time.time() - t0, tuned))
 
     def step():
@@ -276,7 +299,8 @@ def main():
         achieved = credit[dom] / (tot_ms * 1e-3) / 1e12
         peak = PEAK.get(prec, PEAK["fp64"])
         roofline = {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 3), "peak": peak,
-                    "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                    "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+                    "traffic": measured_traffic(args.workload, prec, h_tile_used, group_max_used, dom),
                     "launches": launches, "avg_launch_ms": round(tot_ms / launches, 4),
                     "flops_per_launch": credit[dom] / launches}
 
