@@ -7,6 +7,7 @@
 //     the 64-wide basis tile, padding columns zero;
 //   - D and H dense row-major [N_b][N_b] FP64; n in the caller's point order.
 #include <algorithm>
+#include <type_traits>
 
 #include <hip/hip_runtime.h>
 
@@ -17,6 +18,16 @@ namespace nao {
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+// Pointers into device memory read from the segment tables are generic to the compiler;
+// casting them to the global address space makes it emit global (not flat) loads, stores and
+// atomics, which are counted by vmcnt only and do not hold up waits for LDS results.
+template <typename T> using gp = __attribute__((address_space(1))) T*;
+template <typename T> __device__ inline gp<T> gptr(T* p) { return (gp<T>)p; }
+__device__ inline void gadd(gp<double> p, double v)
+{
+    (void)__hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 // ------------------------------------------------------------------------------------------
 // helpers
@@ -202,7 +213,7 @@ __global__ __launch_bounds__(256) void basis_kernel(const DevSeg* __restrict__ s
             for (int i = threadIdx.x; i < nsp; i += blockDim.x) lds_spline[i] = spl[i];
             __syncthreads();
         }
-        T* __restrict__ out = static_cast<T*>(sg.phi) + u.out_offset;
+        gp<T> __restrict__ out = gptr(static_cast<T*>(sg.phi) + u.out_offset);
         const int64_t npairs = (int64_t)u.n_points * u.n_atoms;
         const double tmax = (double)(nk - 1);
         for (int64_t q = threadIdx.x; q < npairs; q += blockDim.x) {
@@ -218,7 +229,7 @@ __global__ __launch_bounds__(256) void basis_kernel(const DevSeg* __restrict__ s
             const double d2 = dist2_exact(dx, dy, dz);
             const int sp = S->atom_species[atom];
             const int sh0 = S->species_shell_ptr[sp], sh1 = S->species_shell_ptr[sp + 1];
-            T* row = out + (int64_t)pl * u.ld;
+            gp<T> row = out + (int64_t)pl * u.ld;
             if (d2 >= A[3]) {
                 for (int j = sh0; j < sh1; ++j) {
                     const int nf = 2 * S->shell_l[j] + 1;
@@ -384,37 +395,46 @@ __global__ __launch_bounds__(256) void h_kernel(const DevSeg* __restrict__ segs,
         const DevSeg& sg = segs[s];
         const HItem it = static_cast<const HItem*>(sg.items)[sg.item_begin + (b - sg.item_prefix)];
         const DevUnit u = sg.units[it.unit];
-        const T* __restrict__ phi = static_cast<const T*>(sg.phi) + u.out_offset;
-        const double* __restrict__ wv = sg.wv + u.point_begin;
+        gp<const T> __restrict__ phi = gptr(static_cast<const T*>(sg.phi) + u.out_offset);
+        gp<const double> __restrict__ wv = gptr(sg.wv + u.point_begin);
         const int np = u.n_points, ld = u.ld;
         const int I0 = it.ti * TILE, J0 = it.tj * TILE;
         const int n_chunks = (np + KCHUNK - 1) / KCHUNK;
 
+        if (np <= 0) continue;
+        // Loads are issued unconditionally (rows clamped into the unit) and only consumed at
+        // the stash after the next chunk's MFMAs, so that they stay in flight meanwhile.
         T ra[4], rb[4];
+        double rw[4];
         auto fetch = [&](int c) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int e = tid + 256 * q;
-                const int r = e >> 6, col = e & 63;
-                const int p = c * KCHUNK + r;
-                T a = T(0), bb = T(0);
-                if (p < np) {
-                    const T* rowp = phi + (int64_t)p * ld;
-                    a = T((double)rowp[I0 + col] * wv[p]);
-                    bb = rowp[J0 + col];
-                }
-                ra[q] = a;
-                rb[q] = bb;
+                const int pc = min(c * KCHUNK + (e >> 6), np - 1), col = e & 63;
+                gp<const T> rowp = phi + (int64_t)pc * ld;
+                ra[q] = rowp[I0 + col];
+                rb[q] = rowp[J0 + col];
+                rw[q] = wv[pc];
             }
         };
-        auto stash = [&](int buf) {
+        auto stash = [&](int c, int buf) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int e = tid + 256 * q;
-                As[buf][e >> 6][e & 63] = ra[q];
-                Bs[buf][e >> 6][e & 63] = rb[q];
+                const bool ok = c * KCHUNK + (e >> 6) < np;
+                As[buf][e >> 6][e & 63] = ok ? T((double)ra[q] * rw[q]) : T(0);
+                Bs[buf][e >> 6][e & 63] = ok ? rb[q] : T(0);
             }
         };
+        // global indices of this lane's output rows and columns, needed only after the K loop
+        gp<const int32_t> __restrict__ fn = gptr(sg.unit_fn + u.fn_begin);
+        int32_t gI[2][4], gJ[2];
+#pragma unroll
+        for (int ib = 0; ib < 2; ++ib) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) gI[ib][r] = fn[min(I0 + wr * 32 + ib * 16 + M::row(lk, r), u.m - 1)];
+            gJ[ib] = fn[min(J0 + wc * 32 + ib * 16 + lr, u.m - 1)];
+        }
 
         typename M::acc_t acc[2][2];
 #pragma unroll
@@ -422,7 +442,7 @@ __global__ __launch_bounds__(256) void h_kernel(const DevSeg* __restrict__ segs,
 #pragma unroll
             for (int j = 0; j < 2; ++j) acc[i][j] = M::zero();
         fetch(0);
-        stash(0);
+        stash(0, 0);
         __syncthreads();
         for (int c = 0; c < n_chunks; ++c) {
             const int buf = c & 1;
@@ -439,12 +459,11 @@ __global__ __launch_bounds__(256) void h_kernel(const DevSeg* __restrict__ segs,
                 acc[1][0] = M::op(a1, b0, acc[1][0]);
                 acc[1][1] = M::op(a1, b1, acc[1][1]);
             }
-            if (c + 1 < n_chunks) stash(buf ^ 1);
+            if (c + 1 < n_chunks) stash(c + 1, buf ^ 1);
             __syncthreads();
         }
 
-        const int32_t* __restrict__ fn = sg.unit_fn + u.fn_begin;
-        double* __restrict__ H = sg.H;
+        gp<double> __restrict__ H = gptr(sg.H);
         const int64_t ldh = sg.ld;
         const bool diag = it.ti == it.tj;
 #pragma unroll
@@ -456,10 +475,8 @@ __global__ __launch_bounds__(256) void h_kernel(const DevSeg* __restrict__ segs,
                     const int row = wr * 32 + ib * 16 + M::row(lk, r);
                     const int col = wc * 32 + jb * 16 + lr;
                     const int ci = I0 + row, cj = J0 + col;
-                    if (ci < u.m && cj < u.m && (!diag || row <= col)) {
-                        const int64_t gi = fn[ci], gj = fn[cj];
-                        unsafeAtomicAdd(H + gi * ldh + gj, (double)acc[ib][jb][r]);
-                    }
+                    if (ci < u.m && cj < u.m && (!diag || row <= col))
+                        gadd(H + (int64_t)gI[ib][r] * ldh + gJ[jb], (double)acc[ib][jb][r]);
                 }
     }
 }
@@ -485,37 +502,43 @@ __global__ __launch_bounds__(512) void h_kernel_wide(const DevSeg* __restrict__ 
         const DevSeg& sg = segs[s];
         const HItem it = static_cast<const HItem*>(sg.items)[sg.item_begin + (b - sg.item_prefix)];
         const DevUnit u = sg.units[it.unit];
-        const T* __restrict__ phi = static_cast<const T*>(sg.phi) + u.out_offset;
-        const double* __restrict__ wv = sg.wv + u.point_begin;
+        gp<const T> __restrict__ phi = gptr(static_cast<const T*>(sg.phi) + u.out_offset);
+        gp<const double> __restrict__ wv = gptr(sg.wv + u.point_begin);
         const int np = u.n_points, ld = u.ld;
         const int I0 = it.ti * WTILE, J0 = it.tj * WTILE;
         const int n_chunks = (np + KCHUNK - 1) / KCHUNK;
 
+        if (np <= 0) continue;
         T ra[4], rb[4];
+        double rw[4];
         auto fetch = [&](int c) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int e = tid + 512 * q;
-                const int r = e >> 7, col = e & 127;
-                const int p = c * KCHUNK + r;
-                T a = T(0), bb = T(0);
-                if (p < np) {
-                    const T* rowp = phi + (int64_t)p * ld;
-                    a = T((double)rowp[I0 + col] * wv[p]);
-                    bb = rowp[J0 + col];
-                }
-                ra[q] = a;
-                rb[q] = bb;
+                const int pc = min(c * KCHUNK + (e >> 7), np - 1), col = e & 127;
+                gp<const T> rowp = phi + (int64_t)pc * ld;
+                ra[q] = rowp[I0 + col];
+                rb[q] = rowp[J0 + col];
+                rw[q] = wv[pc];
             }
         };
-        auto stash = [&](int buf) {
+        auto stash = [&](int c, int buf) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int e = tid + 512 * q;
-                As[buf][e >> 7][e & 127] = ra[q];
-                Bs[buf][e >> 7][e & 127] = rb[q];
+                const bool ok = c * KCHUNK + (e >> 7) < np;
+                As[buf][e >> 7][e & 127] = ok ? T((double)ra[q] * rw[q]) : T(0);
+                Bs[buf][e >> 7][e & 127] = ok ? rb[q] : T(0);
             }
         };
+        gp<const int32_t> __restrict__ fn = gptr(sg.unit_fn + u.fn_begin);
+        int32_t gI[2][4], gJ[4];
+#pragma unroll
+        for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) gI[ib][r] = fn[min(I0 + wr * 32 + ib * 16 + M::row(lk, r), u.m - 1)];
+#pragma unroll
+        for (int jb = 0; jb < 4; ++jb) gJ[jb] = fn[min(J0 + wc * 64 + jb * 16 + lr, u.m - 1)];
 
         typename M::acc_t acc[2][4];
 #pragma unroll
@@ -523,7 +546,7 @@ __global__ __launch_bounds__(512) void h_kernel_wide(const DevSeg* __restrict__ 
 #pragma unroll
             for (int j = 0; j < 4; ++j) acc[i][j] = M::zero();
         fetch(0);
-        stash(0);
+        stash(0, 0);
         __syncthreads();
         for (int c = 0; c < n_chunks; ++c) {
             const int buf = c & 1;
@@ -541,12 +564,11 @@ __global__ __launch_bounds__(512) void h_kernel_wide(const DevSeg* __restrict__ 
 #pragma unroll
                     for (int j = 0; j < 4; ++j) acc[i][j] = M::op(a[i], bq[j], acc[i][j]);
             }
-            if (c + 1 < n_chunks) stash(buf ^ 1);
+            if (c + 1 < n_chunks) stash(c + 1, buf ^ 1);
             __syncthreads();
         }
 
-        const int32_t* __restrict__ fn = sg.unit_fn + u.fn_begin;
-        double* __restrict__ H = sg.H;
+        gp<double> __restrict__ H = gptr(sg.H);
         const int64_t ldh = sg.ld;
         const bool diag = it.ti == it.tj;
 #pragma unroll
@@ -558,10 +580,8 @@ __global__ __launch_bounds__(512) void h_kernel_wide(const DevSeg* __restrict__ 
                     const int row = wr * 32 + ib * 16 + M::row(lk, r);
                     const int col = wc * 64 + jb * 16 + lr;
                     const int ci = I0 + row, cj = J0 + col;
-                    if (ci < u.m && cj < u.m && (!diag || row <= col)) {
-                        const int64_t gi = fn[ci], gj = fn[cj];
-                        unsafeAtomicAdd(H + gi * ldh + gj, (double)acc[ib][jb][r]);
-                    }
+                    if (ci < u.m && cj < u.m && (!diag || row <= col))
+                        gadd(H + (int64_t)gI[ib][r] * ldh + gJ[jb], (double)acc[ib][jb][r]);
                 }
     }
 }
@@ -578,9 +598,12 @@ template <typename T, int NW>
 __global__ __launch_bounds__(64 * NW) void n_kernel(const DevSeg* __restrict__ segs, int n_segs, int64_t total)
 {
     typedef Mma<T> M;
-    constexpr int NT = 64 * NW;             // threads
-    constexpr int RB = 64 / NW;             // row blocks per wave (16 row x 4 column blocks)
-    constexpr int RS = NW / 4;              // row-block stride between the waves of a column
+    constexpr int NT = 64 * NW;                              // threads
+    constexpr int RB = 64 / NW;                              // row blocks per wave (16 row x 4 column blocks)
+    constexpr int RS = NW / 4;                               // row-block stride between the waves of a column
+    constexpr int NA = MAX_UNIT_POINTS * KCHUNK / NT;        // basis values per thread per chunk
+    constexpr int ND = KCHUNK * TILE / NT;                   // D values per thread per chunk
+    static_assert(ND >= 1 && NA % 2 == 0 && RB % 2 == 0 && NT % TILE == 0, "tile geometry");
     __shared__ T As[2][MAX_UNIT_POINTS][KCHUNK + 1];
     __shared__ T Bs[2][KCHUNK][TILE + 2];
     __shared__ double red[4][MAX_UNIT_POINTS];
@@ -594,98 +617,111 @@ __global__ __launch_bounds__(64 * NW) void n_kernel(const DevSeg* __restrict__ s
         const DevSeg& sg = segs[s];
         const NItem it = static_cast<const NItem*>(sg.items)[sg.item_begin + (b - sg.item_prefix)];
         const DevUnit u = sg.units[it.unit];
-        const T* __restrict__ phi = static_cast<const T*>(sg.phi) + u.out_offset;
-        const int32_t* __restrict__ fn = sg.unit_fn + u.fn_begin;
-        const double* __restrict__ D = sg.D;
+        gp<const T> __restrict__ phi = gptr(static_cast<const T*>(sg.phi) + u.out_offset);
+        gp<const int32_t> __restrict__ fn = gptr(sg.unit_fn + u.fn_begin);
+        gp<const double> __restrict__ D = gptr(sg.D);
         const int64_t ldd = sg.ld;
         const int np = u.n_points, ld = u.ld, m = u.m;
+        if (np <= 0 || m <= 0) continue;
         const int P = (np + 15) >> 4;
         const int J0 = it.tj * TILE;
-        const int n_chunks = (it.tj + 1) * (TILE / KCHUNK);
+        const int n_chunks = (it.tj + 1) * (TILE / KCHUNK);  // chunk c covers columns 16c .. 16c + 15
+        const int cjd = J0 + (tid & (TILE - 1));              // this thread's D column in every chunk
+        const int64_t gjd = fn[min(cjd, m - 1)];
 
-        T pa[MAX_UNIT_POINTS * KCHUNK / NT], pb2[(KCHUNK * TILE + NT - 1) / NT];
-        auto fetch = [&](int c) {
-            const int ti = c / (TILE / KCHUNK);
-            const int c0 = ti * TILE + (c % (TILE / KCHUNK)) * KCHUNK;
-            const bool diag = ti == it.tj;
+        // R = row blocks per wave: RB, or RB / 2 when the unit has at most 128 points.  Loads
+        // are issued with clamped (in-bounds) addresses and consumed only at the stash after
+        // the next chunk's MFMAs; only the list index of a D row is waited for at once.
+        auto run = [&](auto rows) {
+            constexpr int R = decltype(rows)::value;
+            constexpr int NAR = NA * R / RB;
+            T pa[NAR];
+            double pd[ND];
+            // list indices of the D rows: those of chunk c + 1 are loaded during chunk c
+            int32_t gcur[ND], gnxt[ND];
+            auto load_idx = [&](int c, int32_t* g) {
 #pragma unroll
-            for (int q = 0; q < MAX_UNIT_POINTS * KCHUNK / NT; ++q) {
-                const int e = tid + NT * q;
-                const int p = e >> 4, i = e & 15;
-                pa[q] = p < np ? phi[(int64_t)p * ld + c0 + i] : T(0);
-            }
+                for (int q = 0; q < ND; ++q) g[q] = fn[min(16 * c + (tid >> 6) + (NT / TILE) * q, m - 1)];
+            };
+            auto fetch = [&](int c) {
 #pragma unroll
-            for (int q = 0; q < (KCHUNK * TILE + NT - 1) / NT; ++q) {
-                const int e = tid + NT * q;
-                const int i = e >> 6, j = e & 63;
-                const int ci = c0 + i, cj = J0 + j;
-                double val = 0.0;
-                if (ci < m && cj < m) {
-                    const int64_t gi = fn[ci], gj = fn[cj];
-                    if (!diag) val = 2.0 * D[gi * ldd + gj];
-                    else val = ci <= cj ? D[gi * ldd + gj] : D[gj * ldd + gi];
+                for (int q = 0; q < NAR; ++q) {
+                    const int e = tid + NT * q;
+                    pa[q] = phi[(int64_t)min(e >> 4, np - 1) * ld + 16 * c + (e & 15)];
                 }
-                pb2[q] = T(val);
-            }
-        };
-        auto stash = [&](int buf) {
+                const bool diag = c / (TILE / KCHUNK) == it.tj;
 #pragma unroll
-            for (int q = 0; q < MAX_UNIT_POINTS * KCHUNK / NT; ++q) {
-                const int e = tid + NT * q;
-                As[buf][e >> 4][e & 15] = pa[q];
-            }
+                for (int q = 0; q < ND; ++q) {
+                    const int ci = 16 * c + (tid >> 6) + (NT / TILE) * q;
+                    // upper triangle only: the diagonal tile's lower part is read transposed
+                    const bool lower = diag && ci > cjd;
+                    pd[q] = D[lower ? gjd * ldd + gcur[q] : (int64_t)gcur[q] * ldd + gjd];
+                }
+                load_idx(c + 1, gnxt);
+            };
+            auto stash = [&](int c, int buf) {
 #pragma unroll
-            for (int q = 0; q < (KCHUNK * TILE + NT - 1) / NT; ++q) {
-                const int e = tid + NT * q;
-                Bs[buf][e >> 6][e & 63] = pb2[q];
-            }
-        };
+                for (int q = 0; q < ND; ++q) gcur[q] = gnxt[q];
+                const bool diag = c / (TILE / KCHUNK) == it.tj;
+#pragma unroll
+                for (int q = 0; q < NAR; ++q) {
+                    const int e = tid + NT * q;
+                    As[buf][e >> 4][e & 15] = (e >> 4) < np ? pa[q] : T(0);
+                }
+#pragma unroll
+                for (int q = 0; q < ND; ++q) {
+                    const int e = tid + NT * q;
+                    const bool ok = 16 * c + (e >> 6) < m && cjd < m;
+                    Bs[buf][e >> 6][e & 63] = ok ? T(diag ? pd[q] : 2.0 * pd[q]) : T(0);
+                }
+            };
 
-        typename M::acc_t acc[RB];
+            typename M::acc_t acc[R];
 #pragma unroll
-        for (int i = 0; i < RB; ++i) acc[i] = M::zero();
-        fetch(0);
-        stash(0);
-        __syncthreads();
-        for (int c = 0; c < n_chunks; ++c) {
-            const int buf = c & 1;
-            if (c + 1 < n_chunks) fetch(c + 1);
-#pragma unroll
-            for (int kk = 0; kk < KCHUNK / 4; ++kk) {
-                const T bv = Bs[buf][kk * 4 + lk][cb * 16 + lr];
-#pragma unroll
-                for (int q = 0; q < RB; ++q) {
-                    const int pblk = RS * q + rh;
-                    if (pblk < P) acc[q] = M::op(As[buf][pblk * 16 + lr][kk * 4 + lk], bv, acc[q]);
-                }
-            }
-            if (c + 1 < n_chunks) stash(buf ^ 1);
+            for (int i = 0; i < R; ++i) acc[i] = M::zero();
+            load_idx(0, gcur);
+            fetch(0);
+            stash(0, 0);
             __syncthreads();
-        }
+            for (int c = 0; c < n_chunks; ++c) {
+                const int buf = c & 1;
+                if (c + 1 < n_chunks) fetch(c + 1);
+#pragma unroll
+                for (int kk = 0; kk < KCHUNK / 4; ++kk) {
+                    const T bv = Bs[buf][kk * 4 + lk][cb * 16 + lr];
+#pragma unroll
+                    for (int q = 0; q < R; ++q) acc[q] = M::op(As[buf][(RS * q + rh) * 16 + lr][kk * 4 + lk], bv, acc[q]);
+                }
+                if (c + 1 < n_chunks) stash(c + 1, buf ^ 1);
+                __syncthreads();
+            }
 
-        // n_p += sum_j T[p][j] Phi[p][j]
-        const int cj = J0 + cb * 16 + lr;
+            // n_p += sum_j T[p][j] Phi[p][j]
+            const int cj = J0 + cb * 16 + lr;
 #pragma unroll
-        for (int q = 0; q < RB; ++q) {
-            const int pblk = RS * q + rh;
-            if (pblk < P) {
+            for (int q = 0; q < R; ++q) {
+                const int pblk = RS * q + rh;
+                if (pblk < P) {
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int p = pblk * 16 + M::row(lk, r);
-                    double v = 0.0;
-                    if (p < np && cj < m) v = (double)acc[q][r] * (double)phi[(int64_t)p * ld + cj];
-                    v += __shfl_xor(v, 1);
-                    v += __shfl_xor(v, 2);
-                    v += __shfl_xor(v, 4);
-                    v += __shfl_xor(v, 8);
-                    if (lr == 0) red[cb][p] = v;
+                    for (int r = 0; r < 4; ++r) {
+                        const int p = pblk * 16 + M::row(lk, r);
+                        const double f = (double)phi[(int64_t)min(p, np - 1) * ld + cj];
+                        double v = (p < np && cj < m) ? (double)acc[q][r] * f : 0.0;
+                        v += __shfl_xor(v, 1);
+                        v += __shfl_xor(v, 2);
+                        v += __shfl_xor(v, 4);
+                        v += __shfl_xor(v, 8);
+                        if (lr == 0) red[cb][p] = v;
+                    }
                 }
             }
-        }
+        };
+        if (P > 8) run(std::integral_constant<int, RB>{});
+        else run(std::integral_constant<int, RB / 2>{});
         __syncthreads();
         if (tid < np) {
             const double v = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
-            unsafeAtomicAdd(sg.n + sg.sys->perm[u.point_begin + tid], v);
+            gadd(gptr(sg.n) + gptr(sg.sys->perm)[u.point_begin + tid], v);
         }
         __syncthreads();  // red is rewritten by the next item
     }
@@ -744,8 +780,8 @@ __global__ __launch_bounds__(256) void h_kernel_bf16(const DevSeg* __restrict__ 
         const DevSeg& sg = segs[s];
         const HItem it = static_cast<const HItem*>(sg.items)[sg.item_begin + (b - sg.item_prefix)];
         const DevUnit u = sg.units[it.unit];
-        const float* __restrict__ phi = static_cast<const float*>(sg.phi) + u.out_offset;
-        const double* __restrict__ wv = sg.wv + u.point_begin;
+        gp<const float> __restrict__ phi = gptr(static_cast<const float*>(sg.phi) + u.out_offset);
+        gp<const double> __restrict__ wv = gptr(sg.wv + u.point_begin);
         const int np = u.n_points, ld = u.ld;
         const int I0 = it.ti * TILE, J0 = it.tj * TILE;
         const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -767,7 +803,7 @@ __global__ __launch_bounds__(256) void h_kernel_bf16(const DevSeg* __restrict__ 
                 const int p = k0 + r;
                 float a = 0.f, bb = 0.f;
                 if (p < np) {
-                    const float* rowp = phi + (int64_t)p * ld;
+                    gp<const float> rowp = phi + (int64_t)p * ld;
                     a = (float)((double)rowp[I0 + c] * wv[p]);
                     bb = rowp[J0 + c];
                 }
@@ -805,7 +841,7 @@ __global__ __launch_bounds__(256) void h_kernel_bf16(const DevSeg* __restrict__ 
                         acc[i][j][r] = 0.f;
                     }
         }
-        const int32_t* __restrict__ fn = sg.unit_fn + u.fn_begin;
+        gp<const int32_t> __restrict__ fn = gptr(sg.unit_fn + u.fn_begin);
         const bool diag = it.ti == it.tj;
     #pragma unroll
         for (int ib = 0; ib < 2; ++ib)
@@ -816,7 +852,7 @@ __global__ __launch_bounds__(256) void h_kernel_bf16(const DevSeg* __restrict__ 
                     const int row = wr * 32 + ib * 16 + lk * 4 + r, col = wc * 32 + jb * 16 + lr;
                     const int ci = I0 + row, cj = J0 + col;
                     if (ci < u.m && cj < u.m && (!diag || row <= col))
-                        unsafeAtomicAdd(sg.H + (int64_t)fn[ci] * sg.ld + fn[cj], acc64[ib][jb][r]);
+                        gadd(gptr(sg.H) + (int64_t)fn[ci] * sg.ld + fn[cj], acc64[ib][jb][r]);
                 }
     }
 }
@@ -836,9 +872,9 @@ __global__ __launch_bounds__(256) void n_kernel_bf16(const DevSeg* __restrict__ 
         const DevSeg& sg = segs[s];
         const NItem it = static_cast<const NItem*>(sg.items)[sg.item_begin + (b - sg.item_prefix)];
         const DevUnit u = sg.units[it.unit];
-        const float* __restrict__ phi = static_cast<const float*>(sg.phi) + u.out_offset;
-        const int32_t* __restrict__ fn = sg.unit_fn + u.fn_begin;
-        const double* __restrict__ D = sg.D;
+        gp<const float> __restrict__ phi = gptr(static_cast<const float*>(sg.phi) + u.out_offset);
+        gp<const int32_t> __restrict__ fn = gptr(sg.unit_fn + u.fn_begin);
+        gp<const double> __restrict__ D = gptr(sg.D);
         const int64_t ldd = sg.ld;
         const int np = u.n_points, ld = u.ld, m = u.m;
         const int P = (np + 15) >> 4;
@@ -920,7 +956,7 @@ __global__ __launch_bounds__(256) void n_kernel_bf16(const DevSeg* __restrict__ 
         __syncthreads();
         if (tid < np) {
             const double v = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
-            unsafeAtomicAdd(sg.n + sg.sys->perm[u.point_begin + tid], v);
+            gadd(gptr(sg.n) + gptr(sg.sys->perm)[u.point_begin + tid], v);
         }
     }
 }
