@@ -380,7 +380,7 @@ template <> struct Mma<float> {
 // 2x2 MFMA blocks; FP64 atomics into the upper triangle of H.  T = FP32 accumulates a unit
 // (<= 256 points) in FP32 before the FP64 atomics.
 template <typename T>
-__global__ __launch_bounds__(256) void h_kernel(const DevSeg* __restrict__ segs, int n_segs, int64_t total)
+__global__ __launch_bounds__(256, 4) void h_kernel(const DevSeg* __restrict__ segs, int n_segs, int64_t total)
 {
     typedef Mma<T> M;
     __shared__ T As[2][KCHUNK][TILE + 2];
@@ -590,22 +590,25 @@ __global__ __launch_bounds__(512) void h_kernel_wide(const DevSeg* __restrict__ 
 //   T[:, J] = sum_{I <= J} c_IJ Phi[:, I] D[I, J]   (c = 2 off the diagonal tile, 1 on it,
 //             the diagonal tile read from the upper triangle of D),
 //   n_p += sum_{j in J} T[p, j] Phi[p, j].
-// Rows = the unit's points (<= 256: 16 row blocks), K = basis functions in double-buffered
-// chunks of 16; NW waves: wave w owns column block w % 4 and row blocks w / 4, w / 4 + NW / 4,
-// ...  T = FP32 accumulates the whole column tile in FP32; the row dot and the sum over
-// tiles and units are FP64.
-template <typename T, int NW>
+// Rows = the unit's points (<= 256: 16 row blocks), K = basis functions in chunks of KC staged
+// through LDS (two buffers when DB, else one buffer and a second barrier per chunk); the next
+// chunk is prefetched into registers while the MFMAs of the current one run.  NW waves: wave w
+// owns column block w % 4 and row blocks w / 4, w / 4 + NW / 4, ...  T = FP32 accumulates the
+// whole column tile in FP32; the row dot and the sum over tiles and units are FP64.
+template <typename T, int NW, int KC, bool DB>
 __global__ __launch_bounds__(64 * NW) void n_kernel(const DevSeg* __restrict__ segs, int n_segs, int64_t total)
 {
     typedef Mma<T> M;
     constexpr int NT = 64 * NW;                              // threads
     constexpr int RB = 64 / NW;                              // row blocks per wave (16 row x 4 column blocks)
     constexpr int RS = NW / 4;                               // row-block stride between the waves of a column
-    constexpr int NA = MAX_UNIT_POINTS * KCHUNK / NT;        // basis values per thread per chunk
-    constexpr int ND = KCHUNK * TILE / NT;                   // D values per thread per chunk
-    static_assert(ND >= 1 && NA % 2 == 0 && RB % 2 == 0 && NT % TILE == 0, "tile geometry");
-    __shared__ T As[2][MAX_UNIT_POINTS][KCHUNK + 1];
-    __shared__ T Bs[2][KCHUNK][TILE + 2];
+    constexpr int NA = MAX_UNIT_POINTS * KC / NT;            // basis values per thread per chunk
+    constexpr int ND = KC * TILE / NT;                       // D values per thread per chunk
+    constexpr int NB = DB ? 2 : 1;                           // LDS buffers
+    static_assert(ND >= 1 && NA % 2 == 0 && RB % 2 == 0 && NT % TILE == 0 && TILE % KC == 0 && KC % 4 == 0,
+                  "tile geometry");
+    __shared__ T As[NB][MAX_UNIT_POINTS][KC + 1];
+    __shared__ T Bs[NB][KC][TILE + 2];
     __shared__ double red[4][MAX_UNIT_POINTS];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int cb = wave & 3, rh = wave >> 2;  // column block; row blocks rh, rh + RS, ...
@@ -625,13 +628,13 @@ __global__ __launch_bounds__(64 * NW) void n_kernel(const DevSeg* __restrict__ s
         if (np <= 0 || m <= 0) continue;
         const int P = (np + 15) >> 4;
         const int J0 = it.tj * TILE;
-        const int n_chunks = (it.tj + 1) * (TILE / KCHUNK);  // chunk c covers columns 16c .. 16c + 15
+        const int n_chunks = (it.tj + 1) * (TILE / KC);      // chunk c covers columns KC c .. KC c + KC - 1
         const int cjd = J0 + (tid & (TILE - 1));              // this thread's D column in every chunk
         const int64_t gjd = fn[min(cjd, m - 1)];
 
         // R = row blocks per wave: RB, or RB / 2 when the unit has at most 128 points.  Loads
         // are issued with clamped (in-bounds) addresses and consumed only at the stash after
-        // the next chunk's MFMAs; only the list index of a D row is waited for at once.
+        // the current chunk's MFMAs.
         auto run = [&](auto rows) {
             constexpr int R = decltype(rows)::value;
             constexpr int NAR = NA * R / RB;
@@ -641,18 +644,18 @@ __global__ __launch_bounds__(64 * NW) void n_kernel(const DevSeg* __restrict__ s
             int32_t gcur[ND], gnxt[ND];
             auto load_idx = [&](int c, int32_t* g) {
 #pragma unroll
-                for (int q = 0; q < ND; ++q) g[q] = fn[min(16 * c + (tid >> 6) + (NT / TILE) * q, m - 1)];
+                for (int q = 0; q < ND; ++q) g[q] = fn[min(KC * c + (tid >> 6) + (NT / TILE) * q, m - 1)];
             };
             auto fetch = [&](int c) {
 #pragma unroll
                 for (int q = 0; q < NAR; ++q) {
                     const int e = tid + NT * q;
-                    pa[q] = phi[(int64_t)min(e >> 4, np - 1) * ld + 16 * c + (e & 15)];
+                    pa[q] = phi[(int64_t)min(e / KC, np - 1) * ld + KC * c + (e % KC)];
                 }
-                const bool diag = c / (TILE / KCHUNK) == it.tj;
+                const bool diag = c / (TILE / KC) == it.tj;
 #pragma unroll
                 for (int q = 0; q < ND; ++q) {
-                    const int ci = 16 * c + (tid >> 6) + (NT / TILE) * q;
+                    const int ci = KC * c + (tid >> 6) + (NT / TILE) * q;
                     // upper triangle only: the diagonal tile's lower part is read transposed
                     const bool lower = diag && ci > cjd;
                     pd[q] = D[lower ? gjd * ldd + gcur[q] : (int64_t)gcur[q] * ldd + gjd];
@@ -662,16 +665,16 @@ __global__ __launch_bounds__(64 * NW) void n_kernel(const DevSeg* __restrict__ s
             auto stash = [&](int c, int buf) {
 #pragma unroll
                 for (int q = 0; q < ND; ++q) gcur[q] = gnxt[q];
-                const bool diag = c / (TILE / KCHUNK) == it.tj;
+                const bool diag = c / (TILE / KC) == it.tj;
 #pragma unroll
                 for (int q = 0; q < NAR; ++q) {
                     const int e = tid + NT * q;
-                    As[buf][e >> 4][e & 15] = (e >> 4) < np ? pa[q] : T(0);
+                    As[buf][e / KC][e % KC] = (e / KC) < np ? pa[q] : T(0);
                 }
 #pragma unroll
                 for (int q = 0; q < ND; ++q) {
                     const int e = tid + NT * q;
-                    const bool ok = 16 * c + (e >> 6) < m && cjd < m;
+                    const bool ok = KC * c + (e >> 6) < m && cjd < m;
                     Bs[buf][e >> 6][e & 63] = ok ? T(diag ? pd[q] : 2.0 * pd[q]) : T(0);
                 }
             };
@@ -684,15 +687,16 @@ __global__ __launch_bounds__(64 * NW) void n_kernel(const DevSeg* __restrict__ s
             stash(0, 0);
             __syncthreads();
             for (int c = 0; c < n_chunks; ++c) {
-                const int buf = c & 1;
+                const int buf = DB ? (c & 1) : 0;
                 if (c + 1 < n_chunks) fetch(c + 1);
 #pragma unroll
-                for (int kk = 0; kk < KCHUNK / 4; ++kk) {
+                for (int kk = 0; kk < KC / 4; ++kk) {
                     const T bv = Bs[buf][kk * 4 + lk][cb * 16 + lr];
 #pragma unroll
                     for (int q = 0; q < R; ++q) acc[q] = M::op(As[buf][(RS * q + rh) * 16 + lr][kk * 4 + lk], bv, acc[q]);
                 }
-                if (c + 1 < n_chunks) stash(c + 1, buf ^ 1);
+                if (!DB) __syncthreads();  // every wave is done with the only buffer
+                if (c + 1 < n_chunks) stash(c + 1, DB ? (buf ^ 1) : 0);
                 __syncthreads();
             }
 
@@ -993,8 +997,8 @@ hipError_t launch_n(Mode mode, const DevSeg* segs_dev, int n_segs, int64_t n_ite
     if (n_items > 0x7ffffff0) return hipErrorInvalidValue;
     const dim3 g(grid_for(n_items, max_grid)), b(256);
     switch (mode) {
-    case MODE_FP64: hipLaunchKernelGGL((n_kernel<double, 8>), g, dim3(512), 0, st, segs_dev, n_segs, n_items); break;
-    case MODE_FP32: hipLaunchKernelGGL((n_kernel<float, 16>), g, dim3(1024), 0, st, segs_dev, n_segs, n_items); break;
+    case MODE_FP64: hipLaunchKernelGGL((n_kernel<double, 16, 16, true>), g, dim3(1024), 0, st, segs_dev, n_segs, n_items); break;
+    case MODE_FP32: hipLaunchKernelGGL((n_kernel<float, 16, 16, true>), g, dim3(1024), 0, st, segs_dev, n_segs, n_items); break;
     case MODE_BF16X3: hipLaunchKernelGGL(n_kernel_bf16<2>, g, b, 0, st, segs_dev, n_segs, n_items); break;
     case MODE_BF16X6: hipLaunchKernelGGL(n_kernel_bf16<3>, g, b, 0, st, segs_dev, n_segs, n_items); break;
     default: return hipErrorInvalidValue;
