@@ -605,7 +605,7 @@ __global__ __launch_bounds__(64 * NW) void n_kernel(const DevSeg* __restrict__ s
     constexpr int NA = MAX_UNIT_POINTS * KC / NT;            // basis values per thread per chunk
     constexpr int ND = KC * TILE / NT;                       // D values per thread per chunk
     constexpr int NB = DB ? 2 : 1;                           // LDS buffers
-    static_assert(ND >= 1 && NA % 2 == 0 && RB % 2 == 0 && NT % TILE == 0 && TILE % KC == 0 && KC % 4 == 0,
+    static_assert(ND >= 1 && NA % 2 == 0 && RB % 4 == 0 && NT % TILE == 0 && TILE % KC == 0 && KC % 4 == 0,
                   "tile geometry");
     __shared__ T As[NB][MAX_UNIT_POINTS][KC + 1];
     __shared__ T Bs[NB][KC][TILE + 2];
@@ -632,12 +632,15 @@ __global__ __launch_bounds__(64 * NW) void n_kernel(const DevSeg* __restrict__ s
         const int cjd = J0 + (tid & (TILE - 1));              // this thread's D column in every chunk
         const int64_t gjd = fn[min(cjd, m - 1)];
 
-        // R = row blocks per wave: RB, or RB / 2 when the unit has at most 128 points.  Loads
-        // are issued with clamped (in-bounds) addresses and consumed only at the stash after
-        // the current chunk's MFMAs.
-        auto run = [&](auto rows) {
-            constexpr int R = decltype(rows)::value;
-            constexpr int NAR = NA * R / RB;
+        // F = rows staged (RB row blocks per wave's share, or RB / 2 when the unit has at most
+        // 128 points); R = this wave's row blocks below the unit's last one (the waves of one
+        // SIMD share a column block and split the rows, so a SIMD issues MFMAs for exactly the
+        // unit's row blocks).  Loads are issued with clamped (in-bounds) addresses and consumed
+        // only at the stash after the current chunk's MFMAs.
+        auto run = [&](auto rows_staged, auto rows_own) {
+            constexpr int F = decltype(rows_staged)::value;
+            constexpr int R = decltype(rows_own)::value;
+            constexpr int NAR = NA * F / RB;
             T pa[NAR];
             double pd[ND];
             // list indices of the D rows: those of chunk c + 1 are loaded during chunk c
@@ -679,7 +682,7 @@ __global__ __launch_bounds__(64 * NW) void n_kernel(const DevSeg* __restrict__ s
                 }
             };
 
-            typename M::acc_t acc[R];
+            typename M::acc_t acc[R > 0 ? R : 1];
 #pragma unroll
             for (int i = 0; i < R; ++i) acc[i] = M::zero();
             load_idx(0, gcur);
@@ -720,8 +723,19 @@ __global__ __launch_bounds__(64 * NW) void n_kernel(const DevSeg* __restrict__ s
                 }
             }
         };
-        if (P > 8) run(std::integral_constant<int, RB>{});
-        else run(std::integral_constant<int, RB / 2>{});
+        // R is the smallest of RB, 3 RB / 4, RB / 2, RB / 4, 0 that covers this wave's blocks
+        typedef std::integral_constant<int, RB> Full;
+        typedef std::integral_constant<int, RB / 2> Half;
+        const int own = min(RB, (P - rh + RS - 1) / RS);  // wave-uniform
+        if (P > RB / 2 * RS) {  // rows beyond 128: every wave owns more than RB / 2 - 1 blocks
+            if (own > RB * 3 / 4) run(Full{}, Full{});
+            else if (own > RB / 2) run(Full{}, std::integral_constant<int, RB * 3 / 4>{});
+            else run(Full{}, Half{});
+        } else {
+            if (own > RB / 4) run(Half{}, Half{});
+            else if (own > 0) run(Half{}, std::integral_constant<int, RB / 4>{});
+            else run(Half{}, std::integral_constant<int, 0>{});
+        }
         __syncthreads();
         if (tid < np) {
             const double v = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
