@@ -207,7 +207,7 @@ __global__ __launch_bounds__(256) void basis_kernel(const DevSeg* __restrict__ s
         const DevUnit u = sg.units[sg.unit_begin + (b - sg.unit_prefix)];
         const DevSys* S = sg.sys;
         const int nk = S->n_knots;
-        const double* spl = S->spline;
+        gp<const double> spl = gptr(S->spline);
         if (SPLINE_LDS) {
             const int nsp = S->n_radial * (nk - 1) * 4;
             for (int i = threadIdx.x; i < nsp; i += blockDim.x) lds_spline[i] = spl[i];
@@ -219,20 +219,21 @@ __global__ __launch_bounds__(256) void basis_kernel(const DevSeg* __restrict__ s
         for (int64_t q = threadIdx.x; q < npairs; q += blockDim.x) {
             const int pl = (int)(q / u.n_atoms);
             const int ai = (int)(q - (int64_t)pl * u.n_atoms);
-            const int atom = sg.unit_atoms[u.atom_begin + ai];
-            int col = sg.unit_cols[u.atom_begin + ai];
+            const int atom = gptr(sg.unit_atoms)[u.atom_begin + ai];
+            int col = gptr(sg.unit_cols)[u.atom_begin + ai];
             const int64_t p = u.point_begin + pl;
-            const double* A = S->atom_xyzr + 4 * (int64_t)atom;
-            const double dx = S->px[p] - A[0];
-            const double dy = S->py[p] - A[1];
-            const double dz = S->pz[p] - A[2];
+            gp<const double> A = gptr(S->atom_xyzr) + 4 * (int64_t)atom;
+            const double dx = gptr(S->px)[p] - A[0];
+            const double dy = gptr(S->py)[p] - A[1];
+            const double dz = gptr(S->pz)[p] - A[2];
             const double d2 = dist2_exact(dx, dy, dz);
-            const int sp = S->atom_species[atom];
-            const int sh0 = S->species_shell_ptr[sp], sh1 = S->species_shell_ptr[sp + 1];
+            gp<const int32_t> shell_l = gptr(S->shell_l);
+            const int sp = gptr(S->atom_species)[atom];
+            const int sh0 = gptr(S->species_shell_ptr)[sp], sh1 = gptr(S->species_shell_ptr)[sp + 1];
             gp<T> row = out + (int64_t)pl * u.ld;
             if (d2 >= A[3]) {
                 for (int j = sh0; j < sh1; ++j) {
-                    const int nf = 2 * S->shell_l[j] + 1;
+                    const int nf = 2 * shell_l[j] + 1;
                     for (int f = 0; f < nf; ++f) row[col + f] = T(0);
                     col += nf;
                 }
@@ -247,22 +248,28 @@ __global__ __launch_bounds__(256) void basis_kernel(const DevSeg* __restrict__ s
                 uz = dz * ir;
             }
             int lmax = 0;
-            for (int j = sh0; j < sh1; ++j) lmax = max(lmax, S->shell_l[j]);
+            for (int j = sh0; j < sh1; ++j) lmax = max(lmax, shell_l[j]);
             double Y[16];
             real_ylm(ux, uy, uz, lmax, Y);
             const double lnr = r > 0.0 ? log(r) : 0.0;
             for (int j = sh0; j < sh1; ++j) {
-                const int l = S->shell_l[j];
-                const int rr = S->shell_radial[j];
-                const double* par = S->radial_par + 4 * rr;
+                const int l = shell_l[j];
+                const int rr = gptr(S->shell_radial)[j];
+                gp<const double> par = gptr(S->radial_par) + 4 * rr;
                 double R = 0.0;
                 if (d2 < par[1]) {
                     double t = r > par[0] ? (lnr - par[3]) * par[2] : 0.0;
                     t = fmin(fmax(t, 0.0), tmax);
                     const int k = min((int)t, nk - 2);
                     const double w = t - (double)k;
-                    const double* c = (SPLINE_LDS ? lds_spline : spl) + ((int64_t)rr * (nk - 1) + k) * 4;
-                    R = c[0] + w * (c[1] + w * (c[2] + w * c[3]));
+                    const int64_t ci = ((int64_t)rr * (nk - 1) + k) * 4;
+                    if (SPLINE_LDS) {
+                        const double* c = lds_spline + ci;
+                        R = c[0] + w * (c[1] + w * (c[2] + w * c[3]));
+                    } else {
+                        gp<const double> c = spl + ci;
+                        R = c[0] + w * (c[1] + w * (c[2] + w * c[3]));
+                    }
                 }
                 switch (l) {
                 case 0:
@@ -441,31 +448,41 @@ __global__ __launch_bounds__(256, 4) void h_kernel(const DevSeg* __restrict__ se
         for (int i = 0; i < 2; ++i)
 #pragma unroll
             for (int j = 0; j < 2; ++j) acc[i][j] = M::zero();
-        fetch(0);
-        stash(0, 0);
-        __syncthreads();
-        for (int c = 0; c < n_chunks; ++c) {
-            const int buf = c & 1;
-            if (c + 1 < n_chunks) fetch(c + 1);
-#pragma unroll
-            for (int kk = 0; kk < KCHUNK / 4; ++kk) {
-                const int kr = kk * 4 + lk;
-                const T a0 = As[buf][kr][wr * 32 + lr];
-                const T a1 = As[buf][kr][wr * 32 + 16 + lr];
-                const T b0 = Bs[buf][kr][wc * 32 + lr];
-                const T b1 = Bs[buf][kr][wc * 32 + 16 + lr];
-                acc[0][0] = M::op(a0, b0, acc[0][0]);
-                acc[0][1] = M::op(a0, b1, acc[0][1]);
-                acc[1][0] = M::op(a1, b0, acc[1][0]);
-                acc[1][1] = M::op(a1, b1, acc[1][1]);
-            }
-            if (c + 1 < n_chunks) stash(c + 1, buf ^ 1);
+        // On a diagonal tile pair the wave of the strictly lower quarter only stages data.
+        auto k_loop = [&](auto with_mfma) {
+            fetch(0);
+            stash(0, 0);
             __syncthreads();
+            for (int c = 0; c < n_chunks; ++c) {
+                const int buf = c & 1;
+                if (c + 1 < n_chunks) fetch(c + 1);
+                if (decltype(with_mfma)::value) {
+#pragma unroll
+                    for (int kk = 0; kk < KCHUNK / 4; ++kk) {
+                        const int kr = kk * 4 + lk;
+                        const T a0 = As[buf][kr][wr * 32 + lr];
+                        const T a1 = As[buf][kr][wr * 32 + 16 + lr];
+                        const T b0 = Bs[buf][kr][wc * 32 + lr];
+                        const T b1 = Bs[buf][kr][wc * 32 + 16 + lr];
+                        acc[0][0] = M::op(a0, b0, acc[0][0]);
+                        acc[0][1] = M::op(a0, b1, acc[0][1]);
+                        acc[1][0] = M::op(a1, b0, acc[1][0]);
+                        acc[1][1] = M::op(a1, b1, acc[1][1]);
+                    }
+                }
+                if (c + 1 < n_chunks) stash(c + 1, buf ^ 1);
+                __syncthreads();
+            }
+        };
+        const bool diag = it.ti == it.tj;
+        if (diag && wr > wc) {
+            k_loop(std::false_type{});
+            continue;
         }
+        k_loop(std::true_type{});
 
         gp<double> __restrict__ H = gptr(sg.H);
         const int64_t ldh = sg.ld;
-        const bool diag = it.ti == it.tj;
 #pragma unroll
         for (int ib = 0; ib < 2; ++ib)
 #pragma unroll
