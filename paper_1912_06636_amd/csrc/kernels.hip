@@ -798,16 +798,24 @@ __device__ inline f4 mfma_split(const bf8* a, const bf8* b, f4 acc)
     return acc;
 }
 
-constexpr int BK = 32;      // K per bf16 MFMA step
+constexpr int BK = 32;       // K per bf16 MFMA step
 constexpr int BKP = BK + 8;  // padded LDS row (80 bytes: keeps 16-byte alignment)
 
-// Hamiltonian, split-BF16 MFMA (v_mfma_f32_16x16x32_bf16): K = 32 points per step; LDS holds
-// [part][column][point] so every lane reads its 8 consecutive points as one 16-byte vector.
+// Hamiltonian, split-BF16 MFMA (v_mfma_f32_16x16x32_bf16): per item one 64x64 tile pair of a
+// unit, K = 32 points per chunk, four waves of 32x32.  LDS holds [buffer][part][column][point]
+// so that every lane reads its 8 consecutive points as one 16-byte vector; the next chunk's
+// FP32 basis values and FP64 w v are prefetched into registers while the MFMAs of the current
+// one run and are split into bf16 parts at the stash.  The FP32 tile sums move into FP64
+// after every chunk; FP64 atomics into the upper triangle of H.
 template <int NS>
 __global__ __launch_bounds__(256) void h_kernel_bf16(const DevSeg* __restrict__ segs, int n_segs, int64_t total)
 {
-    __shared__ __attribute__((aligned(16))) __bf16 As[NS][TILE][BKP];
-    __shared__ __attribute__((aligned(16))) __bf16 Bs[NS][TILE][BKP];
+    constexpr int NQ = BK * TILE / 256;  // values per thread per chunk and operand
+    __shared__ __attribute__((aligned(16))) __bf16 As[2][NS][TILE][BKP];
+    __shared__ __attribute__((aligned(16))) __bf16 Bs[2][NS][TILE][BKP];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = wave >> 1, wc = wave & 1;
+    const int lr = lane & 15, lk = lane >> 4;
     for (int64_t v_ = blockIdx.x; v_ < xcd_span(total); v_ += gridDim.x) {
         const int64_t b = xcd_item(v_, total);
         if (b >= total) continue;
@@ -818,88 +826,133 @@ __global__ __launch_bounds__(256) void h_kernel_bf16(const DevSeg* __restrict__ 
         gp<const float> __restrict__ phi = gptr(static_cast<const float*>(sg.phi) + u.out_offset);
         gp<const double> __restrict__ wv = gptr(sg.wv + u.point_begin);
         const int np = u.n_points, ld = u.ld;
+        if (np <= 0) continue;
         const int I0 = it.ti * TILE, J0 = it.tj * TILE;
-        const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-        const int wr = wave >> 1, wc = wave & 1;
-        const int lr = lane & 15, lk = lane >> 4;
+        const int n_chunks = (np + BK - 1) / BK;
+
+        float ra[NQ], rb[NQ];
+        double rw[NQ];
+        auto fetch = [&](int c) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const int e = tid + 256 * q;
+                const int pc = min(c * BK + (e >> 6), np - 1), col = e & 63;
+                gp<const float> rowp = phi + (int64_t)pc * ld;
+                ra[q] = rowp[I0 + col];
+                rb[q] = rowp[J0 + col];
+                rw[q] = wv[pc];
+            }
+        };
+        auto stash = [&](int c, int buf) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const int e = tid + 256 * q;
+                const int r = e >> 6, col = e & 63;
+                const bool ok = c * BK + r < np;
+                __bf16 pa[NS], pb[NS];
+                split_bf16<NS>(ok ? (float)((double)ra[q] * rw[q]) : 0.f, pa);
+                split_bf16<NS>(ok ? rb[q] : 0.f, pb);
+#pragma unroll
+                for (int t = 0; t < NS; ++t) {
+                    As[buf][t][col][r] = pa[t];
+                    Bs[buf][t][col][r] = pb[t];
+                }
+            }
+        };
+        gp<const int32_t> __restrict__ fn = gptr(sg.unit_fn + u.fn_begin);
+        int32_t gI[2][4], gJ[2];
+#pragma unroll
+        for (int ib = 0; ib < 2; ++ib) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) gI[ib][r] = fn[min(I0 + wr * 32 + ib * 16 + lk * 4 + r, u.m - 1)];
+            gJ[ib] = fn[min(J0 + wc * 32 + ib * 16 + lr, u.m - 1)];
+        }
+
         f4 acc[2][2];
         d4 acc64[2][2];
-    #pragma unroll
+#pragma unroll
         for (int i = 0; i < 2; ++i)
-    #pragma unroll
+#pragma unroll
             for (int j = 0; j < 2; ++j) {
                 acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
                 acc64[i][j] = d4{0.0, 0.0, 0.0, 0.0};
             }
-        for (int k0 = 0; k0 < np; k0 += BK) {
-    #pragma unroll
-            for (int e = tid; e < BK * TILE; e += 256) {
-                const int r = e >> 6, c = e & 63;
-                const int p = k0 + r;
-                float a = 0.f, bb = 0.f;
-                if (p < np) {
-                    gp<const float> rowp = phi + (int64_t)p * ld;
-                    a = (float)((double)rowp[I0 + c] * wv[p]);
-                    bb = rowp[J0 + c];
-                }
-                __bf16 pa[NS], pb[NS];
-                split_bf16<NS>(a, pa);
-                split_bf16<NS>(bb, pb);
-    #pragma unroll
-                for (int q = 0; q < NS; ++q) {
-                    As[q][c][r] = pa[q];
-                    Bs[q][c][r] = pb[q];
-                }
-            }
+        auto k_loop = [&](auto with_mfma) {
+            fetch(0);
+            stash(0, 0);
             __syncthreads();
-            bf8 a0[NS], a1[NS], b0[NS], b1[NS];
-    #pragma unroll
-            for (int q = 0; q < NS; ++q) {
-                a0[q] = *reinterpret_cast<const bf8*>(&As[q][wr * 32 + lr][lk * 8]);
-                a1[q] = *reinterpret_cast<const bf8*>(&As[q][wr * 32 + 16 + lr][lk * 8]);
-                b0[q] = *reinterpret_cast<const bf8*>(&Bs[q][wc * 32 + lr][lk * 8]);
-                b1[q] = *reinterpret_cast<const bf8*>(&Bs[q][wc * 32 + 16 + lr][lk * 8]);
-            }
-            acc[0][0] = mfma_split<NS>(a0, b0, acc[0][0]);
-            acc[0][1] = mfma_split<NS>(a0, b1, acc[0][1]);
-            acc[1][0] = mfma_split<NS>(a1, b0, acc[1][0]);
-            acc[1][1] = mfma_split<NS>(a1, b1, acc[1][1]);
-            __syncthreads();
-            // every 32 points: move the FP32 sums into FP64
-    #pragma unroll
-            for (int i = 0; i < 2; ++i)
-    #pragma unroll
-                for (int j = 0; j < 2; ++j)
-    #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        acc64[i][j][r] += (double)acc[i][j][r];
-                        acc[i][j][r] = 0.f;
+            for (int c = 0; c < n_chunks; ++c) {
+                const int buf = c & 1;
+                if (c + 1 < n_chunks) fetch(c + 1);
+                if (decltype(with_mfma)::value) {
+                    bf8 a0[NS], a1[NS], b0[NS], b1[NS];
+#pragma unroll
+                    for (int t = 0; t < NS; ++t) {
+                        a0[t] = *reinterpret_cast<const bf8*>(&As[buf][t][wr * 32 + lr][lk * 8]);
+                        a1[t] = *reinterpret_cast<const bf8*>(&As[buf][t][wr * 32 + 16 + lr][lk * 8]);
+                        b0[t] = *reinterpret_cast<const bf8*>(&Bs[buf][t][wc * 32 + lr][lk * 8]);
+                        b1[t] = *reinterpret_cast<const bf8*>(&Bs[buf][t][wc * 32 + 16 + lr][lk * 8]);
                     }
-        }
-        gp<const int32_t> __restrict__ fn = gptr(sg.unit_fn + u.fn_begin);
+                    acc[0][0] = mfma_split<NS>(a0, b0, acc[0][0]);
+                    acc[0][1] = mfma_split<NS>(a0, b1, acc[0][1]);
+                    acc[1][0] = mfma_split<NS>(a1, b0, acc[1][0]);
+                    acc[1][1] = mfma_split<NS>(a1, b1, acc[1][1]);
+                    // every chunk of 32 points: move the FP32 sums into FP64
+#pragma unroll
+                    for (int i = 0; i < 2; ++i)
+#pragma unroll
+                        for (int j = 0; j < 2; ++j)
+#pragma unroll
+                            for (int r = 0; r < 4; ++r) {
+                                acc64[i][j][r] += (double)acc[i][j][r];
+                                acc[i][j][r] = 0.f;
+                            }
+                }
+                if (c + 1 < n_chunks) stash(c + 1, buf ^ 1);
+                __syncthreads();
+            }
+        };
         const bool diag = it.ti == it.tj;
-    #pragma unroll
+        if (diag && wr > wc) {  // the strictly lower quarter of a diagonal tile pair only stages data
+            k_loop(std::false_type{});
+            continue;
+        }
+        k_loop(std::true_type{});
+        gp<double> __restrict__ H = gptr(sg.H);
+        const int64_t ldh = sg.ld;
+#pragma unroll
         for (int ib = 0; ib < 2; ++ib)
-    #pragma unroll
+#pragma unroll
             for (int jb = 0; jb < 2; ++jb)
-    #pragma unroll
+#pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int row = wr * 32 + ib * 16 + lk * 4 + r, col = wc * 32 + jb * 16 + lr;
                     const int ci = I0 + row, cj = J0 + col;
                     if (ci < u.m && cj < u.m && (!diag || row <= col))
-                        gadd(gptr(sg.H) + (int64_t)fn[ci] * sg.ld + fn[cj], acc64[ib][jb][r]);
+                        gadd(H + (int64_t)gI[ib][r] * ldh + gJ[jb], acc64[ib][jb][r]);
                 }
     }
 }
 
-// Density, split-BF16 MFMA: K = 32 functions per step.  A (points x functions) in LDS as
-// [part][point][function]; B (functions x columns) as [part][column][function].
-template <int NS>
-__global__ __launch_bounds__(256) void n_kernel_bf16(const DevSeg* __restrict__ segs, int n_segs, int64_t total)
+// Density, split-BF16 MFMA: per item one 64-wide column tile J of a unit, K = 32 functions per
+// chunk; sixteen waves as in n_kernel (wave w: column block w % 4, row blocks w / 4 + 4 q).  A
+// (points x functions) in LDS as [part][point][function], B (functions x columns) as
+// [part][column][function]; NB LDS buffers (one buffer adds a barrier per chunk).  The FP32
+// sums move into FP64 after every 64-function tile; the row dot and the sums over tiles and
+// units are FP64.
+template <int NS, int NB>
+__global__ __launch_bounds__(1024) void n_kernel_bf16(const DevSeg* __restrict__ segs, int n_segs, int64_t total)
 {
-    __shared__ __attribute__((aligned(16))) __bf16 As[NS][MAX_UNIT_POINTS][BKP];
-    __shared__ __attribute__((aligned(16))) __bf16 Bs[NS][TILE][BKP];
+    constexpr int NT = 1024, RB = 4, RS = 4;
+    constexpr int NA = MAX_UNIT_POINTS * BK / NT;  // basis values per thread per chunk (8)
+    constexpr int ND = BK * TILE / NT;             // D values per thread per chunk (2)
+    constexpr int CPT = TILE / BK;                 // chunks per tile (2)
+    __shared__ __attribute__((aligned(16))) __bf16 As[NB][NS][MAX_UNIT_POINTS][BKP];
+    __shared__ __attribute__((aligned(16))) __bf16 Bs[NB][NS][TILE][BKP];
     __shared__ double red[4][MAX_UNIT_POINTS];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int cb = wave & 3, rh = wave >> 2;
+    const int lr = lane & 15, lk = lane >> 4;
     for (int64_t v_ = blockIdx.x; v_ < xcd_span(total); v_ += gridDim.x) {
         const int64_t b = xcd_item(v_, total);
         if (b >= total) continue;
@@ -912,87 +965,140 @@ __global__ __launch_bounds__(256) void n_kernel_bf16(const DevSeg* __restrict__ 
         gp<const double> __restrict__ D = gptr(sg.D);
         const int64_t ldd = sg.ld;
         const int np = u.n_points, ld = u.ld, m = u.m;
+        if (np <= 0 || m <= 0) continue;
         const int P = (np + 15) >> 4;
         const int J0 = it.tj * TILE;
-        const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-        const int lr = lane & 15, lk = lane >> 4;
-        f4 acc[MAX_UNIT_POINTS / 16];
-        d4 acc64[MAX_UNIT_POINTS / 16];
-    #pragma unroll
-        for (int i = 0; i < MAX_UNIT_POINTS / 16; ++i) {
-            acc[i] = f4{0.f, 0.f, 0.f, 0.f};
-            acc64[i] = d4{0.0, 0.0, 0.0, 0.0};
-        }
-        for (int ti = 0; ti <= it.tj; ++ti) {
-            const bool diag = ti == it.tj;
-            for (int i0 = 0; i0 < TILE; i0 += BK) {
-                const int c0 = ti * TILE + i0;
-                for (int e = tid; e < MAX_UNIT_POINTS * BK; e += 256) {
-                    const int p = e >> 5, i = e & 31;
-                    const float x = p < np ? phi[(int64_t)p * ld + c0 + i] : 0.f;
+        const int n_chunks = (it.tj + 1) * CPT;  // chunk c covers functions 32 c .. 32 c + 31
+        const int cjd = J0 + (tid & (TILE - 1));
+        const int64_t gjd = fn[min(cjd, m - 1)];
+
+        auto run = [&](auto rows_staged, auto rows_own) {
+            constexpr int F = decltype(rows_staged)::value;
+            constexpr int R = decltype(rows_own)::value;
+            constexpr int NAR = NA * F / RB;
+            float pa[NAR];
+            double pd[ND];
+            int32_t gcur[ND], gnxt[ND];
+            auto load_idx = [&](int c, int32_t* g) {
+#pragma unroll
+                for (int q = 0; q < ND; ++q) g[q] = fn[min(BK * c + (tid >> 6) + (NT / TILE) * q, m - 1)];
+            };
+            auto fetch = [&](int c) {
+#pragma unroll
+                for (int q = 0; q < NAR; ++q) {
+                    const int e = tid + NT * q;
+                    pa[q] = phi[(int64_t)min(e / BK, np - 1) * ld + BK * c + (e % BK)];
+                }
+                const bool diag = c / CPT == it.tj;
+#pragma unroll
+                for (int q = 0; q < ND; ++q) {
+                    const int ci = BK * c + (tid >> 6) + (NT / TILE) * q;
+                    const bool lower = diag && ci > cjd;
+                    pd[q] = D[lower ? gjd * ldd + gcur[q] : (int64_t)gcur[q] * ldd + gjd];
+                }
+                load_idx(c + 1, gnxt);
+            };
+            auto stash = [&](int c, int buf) {
+#pragma unroll
+                for (int q = 0; q < ND; ++q) gcur[q] = gnxt[q];
+                const bool diag = c / CPT == it.tj;
+#pragma unroll
+                for (int q = 0; q < NAR; ++q) {
+                    const int e = tid + NT * q;
                     __bf16 px[NS];
-                    split_bf16<NS>(x, px);
-    #pragma unroll
-                    for (int q = 0; q < NS; ++q) As[q][p][i] = px[q];
+                    split_bf16<NS>((e / BK) < np ? pa[q] : 0.f, px);
+#pragma unroll
+                    for (int t = 0; t < NS; ++t) As[buf][t][e / BK][e % BK] = px[t];
                 }
-                for (int e = tid; e < BK * TILE; e += 256) {
+#pragma unroll
+                for (int q = 0; q < ND; ++q) {
+                    const int e = tid + NT * q;
                     const int i = e >> 6, j = e & 63;
-                    const int ci = c0 + i, cj = J0 + j;
-                    double val = 0.0;
-                    if (ci < m && cj < m) {
-                        const int64_t gi = fn[ci], gj = fn[cj];
-                        if (!diag) val = 2.0 * D[gi * ldd + gj];
-                        else val = ci <= cj ? D[gi * ldd + gj] : D[gj * ldd + gi];
-                    }
+                    const bool ok = BK * c + i < m && cjd < m;
                     __bf16 pv[NS];
-                    split_bf16<NS>((float)val, pv);
-    #pragma unroll
-                    for (int q = 0; q < NS; ++q) Bs[q][j][i] = pv[q];
+                    split_bf16<NS>(ok ? (float)(diag ? pd[q] : 2.0 * pd[q]) : 0.f, pv);
+#pragma unroll
+                    for (int t = 0; t < NS; ++t) Bs[buf][t][j][i] = pv[t];
                 }
-                __syncthreads();
-                bf8 bv[NS];
-    #pragma unroll
-                for (int q = 0; q < NS; ++q) bv[q] = *reinterpret_cast<const bf8*>(&Bs[q][wave * 16 + lr][lk * 8]);
-    #pragma unroll
-                for (int pb = 0; pb < MAX_UNIT_POINTS / 16; ++pb)
-                    if (pb < P) {
+            };
+
+            f4 acc[R > 0 ? R : 1];
+            d4 acc64[R > 0 ? R : 1];
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                acc[i] = f4{0.f, 0.f, 0.f, 0.f};
+                acc64[i] = d4{0.0, 0.0, 0.0, 0.0};
+            }
+            load_idx(0, gcur);
+            fetch(0);
+            stash(0, 0);
+            __syncthreads();
+            for (int c = 0; c < n_chunks; ++c) {
+                const int buf = NB == 2 ? (c & 1) : 0;
+                if (c + 1 < n_chunks) fetch(c + 1);
+                if (R > 0) {
+                    bf8 bv[NS];
+#pragma unroll
+                    for (int t = 0; t < NS; ++t) bv[t] = *reinterpret_cast<const bf8*>(&Bs[buf][t][cb * 16 + lr][lk * 8]);
+#pragma unroll
+                    for (int q = 0; q < R; ++q) {
                         bf8 av[NS];
-    #pragma unroll
-                        for (int q = 0; q < NS; ++q) av[q] = *reinterpret_cast<const bf8*>(&As[q][pb * 16 + lr][lk * 8]);
-                        acc[pb] = mfma_split<NS>(av, bv, acc[pb]);
+#pragma unroll
+                        for (int t = 0; t < NS; ++t)
+                            av[t] = *reinterpret_cast<const bf8*>(&As[buf][t][(RS * q + rh) * 16 + lr][lk * 8]);
+                        acc[q] = mfma_split<NS>(av, bv, acc[q]);
                     }
+                    if (c % CPT == CPT - 1) {  // end of a 64-function tile
+#pragma unroll
+                        for (int q = 0; q < R; ++q)
+#pragma unroll
+                            for (int r = 0; r < 4; ++r) {
+                                acc64[q][r] += (double)acc[q][r];
+                                acc[q][r] = 0.f;
+                            }
+                    }
+                }
+                if (NB == 1) __syncthreads();
+                if (c + 1 < n_chunks) stash(c + 1, NB == 2 ? (buf ^ 1) : 0);
                 __syncthreads();
             }
-    #pragma unroll
-            for (int pb = 0; pb < MAX_UNIT_POINTS / 16; ++pb)
-    #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    acc64[pb][r] += (double)acc[pb][r];
-                    acc[pb][r] = 0.f;
-                }
-        }
-        const int cj = J0 + wave * 16 + lr;
-    #pragma unroll
-        for (int pb = 0; pb < MAX_UNIT_POINTS / 16; ++pb) {
-            if (pb < P) {
-    #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int p = pb * 16 + lk * 4 + r;
-                    double v = 0.0;
-                    if (p < np && cj < m) v = acc64[pb][r] * (double)phi[(int64_t)p * ld + cj];
-                    v += __shfl_xor(v, 1);
-                    v += __shfl_xor(v, 2);
-                    v += __shfl_xor(v, 4);
-                    v += __shfl_xor(v, 8);
-                    if (lr == 0) red[wave][p] = v;
+            const int cj = J0 + cb * 16 + lr;
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                const int pblk = RS * q + rh;
+                if (pblk < P) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int p = pblk * 16 + lk * 4 + r;
+                        const double f = (double)phi[(int64_t)min(p, np - 1) * ld + cj];
+                        double v = (p < np && cj < m) ? acc64[q][r] * f : 0.0;
+                        v += __shfl_xor(v, 1);
+                        v += __shfl_xor(v, 2);
+                        v += __shfl_xor(v, 4);
+                        v += __shfl_xor(v, 8);
+                        if (lr == 0) red[cb][p] = v;
+                    }
                 }
             }
+        };
+        typedef std::integral_constant<int, RB> Full;
+        typedef std::integral_constant<int, RB / 2> Half;
+        const int own = min(RB, (P - rh + RS - 1) / RS);
+        if (P > RB / 2 * RS) {
+            if (own > RB * 3 / 4) run(Full{}, Full{});
+            else if (own > RB / 2) run(Full{}, std::integral_constant<int, RB * 3 / 4>{});
+            else run(Full{}, Half{});
+        } else {
+            if (own > RB / 4) run(Half{}, Half{});
+            else if (own > 0) run(Half{}, std::integral_constant<int, RB / 4>{});
+            else run(Half{}, std::integral_constant<int, 0>{});
         }
         __syncthreads();
         if (tid < np) {
             const double v = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
             gadd(gptr(sg.n) + gptr(sg.sys->perm)[u.point_begin + tid], v);
         }
+        __syncthreads();  // red is rewritten by the next item
     }
 }
 
@@ -1030,8 +1136,8 @@ hipError_t launch_n(Mode mode, const DevSeg* segs_dev, int n_segs, int64_t n_ite
     switch (mode) {
     case MODE_FP64: hipLaunchKernelGGL((n_kernel<double, 16, 16, true>), g, dim3(1024), 0, st, segs_dev, n_segs, n_items); break;
     case MODE_FP32: hipLaunchKernelGGL((n_kernel<float, 16, 16, true>), g, dim3(1024), 0, st, segs_dev, n_segs, n_items); break;
-    case MODE_BF16X3: hipLaunchKernelGGL(n_kernel_bf16<2>, g, b, 0, st, segs_dev, n_segs, n_items); break;
-    case MODE_BF16X6: hipLaunchKernelGGL(n_kernel_bf16<3>, g, b, 0, st, segs_dev, n_segs, n_items); break;
+    case MODE_BF16X3: hipLaunchKernelGGL((n_kernel_bf16<2, 2>), g, dim3(1024), 0, st, segs_dev, n_segs, n_items); break;
+    case MODE_BF16X6: hipLaunchKernelGGL((n_kernel_bf16<3, 1>), g, dim3(1024), 0, st, segs_dev, n_segs, n_items); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
