@@ -28,6 +28,8 @@ struct DevSys {
     const double* spline;              // [n_radial][n_knots-1][4] polynomial coefficients
     const int32_t* species_fn_ptr;     // [n_species+1] into fn_code
     const int32_t* fn_code;            // per species function: (shell within species << 4) | lm
+    int32_t n_species;
+    int32_t n_shells;
     int32_t n_radial;
     int32_t n_knots;
     int64_t n_basis;

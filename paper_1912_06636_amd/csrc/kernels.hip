@@ -192,12 +192,26 @@ __device__ inline int slot_of(const int32_t* __restrict__ cols, int na, int col)
     return lo;
 }
 
+constexpr int BASIS_ATOMS = 256;   // atoms of a unit staged in LDS
+constexpr int BASIS_SHELLS = 128;  // shells of a system staged in LDS
+
+// Basis values of execution units: one workgroup per unit; threads over (point, atom) pairs
+// with the atom fastest, each writing all functions of its atom.  The unit's atoms (position,
+// cutoff, species, first column) and the system's shell tables (l, radial function and its
+// parameters) are staged in LDS first, so that a pair's chain of table lookups stays on chip;
+// a unit or system larger than the staging arrays reads them from global memory instead.
 template <typename T, bool SPLINE_LDS>
 __global__ __launch_bounds__(256) void basis_kernel(const DevSeg* __restrict__ segs, int n_segs, int64_t total,
                                                     int spline_lds)
 {
     extern __shared__ double lds_spline[];
+    __shared__ double s_atom[BASIS_ATOMS][4];  // x, y, z, (largest cutoff)^2
+    __shared__ int32_t s_aspc[BASIS_ATOMS][2];  // species, first column in the unit
+    __shared__ double s_par[BASIS_SHELLS][4];  // rmin, rcut^2, 1/Delta, ln rmin of the shell's radial
+    __shared__ int32_t s_shell[BASIS_SHELLS][2];  // l, radial function
+    __shared__ int32_t s_shptr[BASIS_SHELLS + 1];
     (void)spline_lds;  // the launcher sized the dynamic LDS for the table
+    const int tid = threadIdx.x;
     for (int64_t v_ = blockIdx.x; v_ < xcd_span(total); v_ += gridDim.x) {
         const int64_t b = xcd_item(v_, total);
         if (b >= total) continue;
@@ -207,98 +221,137 @@ __global__ __launch_bounds__(256) void basis_kernel(const DevSeg* __restrict__ s
         const DevUnit u = sg.units[sg.unit_begin + (b - sg.unit_prefix)];
         const DevSys* S = sg.sys;
         const int nk = S->n_knots;
+        const int na = u.n_atoms, n_sp = S->n_species, n_sh = S->n_shells;
         gp<const double> spl = gptr(S->spline);
+        gp<const int32_t> uat = gptr(sg.unit_atoms) + u.atom_begin;
+        gp<const int32_t> ucol = gptr(sg.unit_cols) + u.atom_begin;
+        gp<const double> axyz = gptr(S->atom_xyzr);
+        gp<const int32_t> aspecies = gptr(S->atom_species);
+        gp<const int32_t> shell_ptr = gptr(S->species_shell_ptr);
+        gp<const int32_t> shell_l = gptr(S->shell_l);
+        gp<const int32_t> shell_rad = gptr(S->shell_radial);
+        gp<const double> rpar = gptr(S->radial_par);
+        const bool staged = na <= BASIS_ATOMS && n_sh <= BASIS_SHELLS && n_sp <= BASIS_SHELLS;  // uniform
         if (SPLINE_LDS) {
             const int nsp = S->n_radial * (nk - 1) * 4;
-            for (int i = threadIdx.x; i < nsp; i += blockDim.x) lds_spline[i] = spl[i];
-            __syncthreads();
+            for (int i = tid; i < nsp; i += blockDim.x) lds_spline[i] = spl[i];
         }
+        if (staged) {
+            for (int ai = tid; ai < na; ai += blockDim.x) {
+                const int atom = uat[ai];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) s_atom[ai][k] = axyz[4 * (int64_t)atom + k];
+                s_aspc[ai][0] = aspecies[atom];
+                s_aspc[ai][1] = ucol[ai];
+            }
+            for (int j = tid; j < n_sh; j += blockDim.x) {
+                const int rr = shell_rad[j];
+                s_shell[j][0] = shell_l[j];
+                s_shell[j][1] = rr;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) s_par[j][k] = rpar[4 * rr + k];
+            }
+            for (int k = tid; k <= n_sp; k += blockDim.x) s_shptr[k] = shell_ptr[k];
+        }
+        if (SPLINE_LDS || staged) __syncthreads();
         gp<T> __restrict__ out = gptr(static_cast<T*>(sg.phi) + u.out_offset);
-        const int64_t npairs = (int64_t)u.n_points * u.n_atoms;
+        const int64_t npairs = (int64_t)u.n_points * na;
         const double tmax = (double)(nk - 1);
-        for (int64_t q = threadIdx.x; q < npairs; q += blockDim.x) {
-            const int pl = (int)(q / u.n_atoms);
-            const int ai = (int)(q - (int64_t)pl * u.n_atoms);
-            const int atom = gptr(sg.unit_atoms)[u.atom_begin + ai];
-            int col = gptr(sg.unit_cols)[u.atom_begin + ai];
-            const int64_t p = u.point_begin + pl;
-            gp<const double> A = gptr(S->atom_xyzr) + 4 * (int64_t)atom;
-            const double dx = gptr(S->px)[p] - A[0];
-            const double dy = gptr(S->py)[p] - A[1];
-            const double dz = gptr(S->pz)[p] - A[2];
-            const double d2 = dist2_exact(dx, dy, dz);
-            gp<const int32_t> shell_l = gptr(S->shell_l);
-            const int sp = gptr(S->atom_species)[atom];
-            const int sh0 = gptr(S->species_shell_ptr)[sp], sh1 = gptr(S->species_shell_ptr)[sp + 1];
-            gp<T> row = out + (int64_t)pl * u.ld;
-            if (d2 >= A[3]) {
-                for (int j = sh0; j < sh1; ++j) {
-                    const int nf = 2 * shell_l[j] + 1;
-                    for (int f = 0; f < nf; ++f) row[col + f] = T(0);
-                    col += nf;
+
+        auto pairs = [&](auto on_chip) {
+            constexpr bool ST = decltype(on_chip)::value;
+            for (int64_t q = tid; q < npairs; q += blockDim.x) {
+                const int pl = (int)(q / na);
+                const int ai = (int)(q - (int64_t)pl * na);
+                const int atom = ST ? 0 : uat[ai];
+                int col = ST ? s_aspc[ai][1] : ucol[ai];
+                const int64_t p = u.point_begin + pl;
+                const double ax = ST ? s_atom[ai][0] : axyz[4 * (int64_t)atom];
+                const double ay = ST ? s_atom[ai][1] : axyz[4 * (int64_t)atom + 1];
+                const double az = ST ? s_atom[ai][2] : axyz[4 * (int64_t)atom + 2];
+                const double arc2 = ST ? s_atom[ai][3] : axyz[4 * (int64_t)atom + 3];
+                const double dx = gptr(S->px)[p] - ax;
+                const double dy = gptr(S->py)[p] - ay;
+                const double dz = gptr(S->pz)[p] - az;
+                const double d2 = dist2_exact(dx, dy, dz);
+                const int sp = ST ? s_aspc[ai][0] : aspecies[atom];
+                const int sh0 = ST ? s_shptr[sp] : shell_ptr[sp];
+                const int sh1 = ST ? s_shptr[sp + 1] : shell_ptr[sp + 1];
+                gp<T> row = out + (int64_t)pl * u.ld;
+                if (d2 >= arc2) {
+                    for (int j = sh0; j < sh1; ++j) {
+                        const int nf = 2 * (ST ? s_shell[j][0] : shell_l[j]) + 1;
+                        for (int f = 0; f < nf; ++f) row[col + f] = T(0);
+                        col += nf;
+                    }
+                    continue;
                 }
-                continue;
-            }
-            const double r = sqrt(d2);
-            double ux = 0.0, uy = 0.0, uz = 1.0;
-            if (r > 0.0) {
-                const double ir = 1.0 / r;
-                ux = dx * ir;
-                uy = dy * ir;
-                uz = dz * ir;
-            }
-            int lmax = 0;
-            for (int j = sh0; j < sh1; ++j) lmax = max(lmax, shell_l[j]);
-            double Y[16];
-            real_ylm(ux, uy, uz, lmax, Y);
-            const double lnr = r > 0.0 ? log(r) : 0.0;
-            for (int j = sh0; j < sh1; ++j) {
-                const int l = shell_l[j];
-                const int rr = gptr(S->shell_radial)[j];
-                gp<const double> par = gptr(S->radial_par) + 4 * rr;
-                double R = 0.0;
-                if (d2 < par[1]) {
-                    double t = r > par[0] ? (lnr - par[3]) * par[2] : 0.0;
-                    t = fmin(fmax(t, 0.0), tmax);
-                    const int k = min((int)t, nk - 2);
-                    const double w = t - (double)k;
-                    const int64_t ci = ((int64_t)rr * (nk - 1) + k) * 4;
-                    if (SPLINE_LDS) {
-                        const double* c = lds_spline + ci;
-                        R = c[0] + w * (c[1] + w * (c[2] + w * c[3]));
-                    } else {
-                        gp<const double> c = spl + ci;
-                        R = c[0] + w * (c[1] + w * (c[2] + w * c[3]));
+                const double r = sqrt(d2);
+                double ux = 0.0, uy = 0.0, uz = 1.0;
+                if (r > 0.0) {
+                    const double ir = 1.0 / r;
+                    ux = dx * ir;
+                    uy = dy * ir;
+                    uz = dz * ir;
+                }
+                int lmax = 0;
+                for (int j = sh0; j < sh1; ++j) lmax = max(lmax, ST ? s_shell[j][0] : shell_l[j]);
+                double Y[16];
+                real_ylm(ux, uy, uz, lmax, Y);
+                const double lnr = r > 0.0 ? log(r) : 0.0;
+                for (int j = sh0; j < sh1; ++j) {
+                    const int l = ST ? s_shell[j][0] : shell_l[j];
+                    const int rr = ST ? s_shell[j][1] : shell_rad[j];
+                    const double rmin = ST ? s_par[j][0] : rpar[4 * rr];
+                    const double rc2 = ST ? s_par[j][1] : rpar[4 * rr + 1];
+                    const double idel = ST ? s_par[j][2] : rpar[4 * rr + 2];
+                    const double lnmin = ST ? s_par[j][3] : rpar[4 * rr + 3];
+                    double R = 0.0;
+                    if (d2 < rc2) {
+                        double t = r > rmin ? (lnr - lnmin) * idel : 0.0;
+                        t = fmin(fmax(t, 0.0), tmax);
+                        const int k = min((int)t, nk - 2);
+                        const double w = t - (double)k;
+                        const int64_t ci = ((int64_t)rr * (nk - 1) + k) * 4;
+                        if (SPLINE_LDS) {
+                            const double* c = lds_spline + ci;
+                            R = c[0] + w * (c[1] + w * (c[2] + w * c[3]));
+                        } else {
+                            gp<const double> c = spl + ci;
+                            R = c[0] + w * (c[1] + w * (c[2] + w * c[3]));
+                        }
+                    }
+                    switch (l) {
+                    case 0:
+                        row[col] = T(R * Y[0]);
+                        col += 1;
+                        break;
+                    case 1:
+                        row[col] = T(R * Y[1]);
+                        row[col + 1] = T(R * Y[2]);
+                        row[col + 2] = T(R * Y[3]);
+                        col += 3;
+                        break;
+                    case 2:
+#pragma unroll
+                        for (int f = 0; f < 5; ++f) row[col + f] = T(R * Y[4 + f]);
+                        col += 5;
+                        break;
+                    default:
+#pragma unroll
+                        for (int f = 0; f < 7; ++f) row[col + f] = T(R * Y[9 + f]);
+                        col += 7;
+                        break;
                     }
                 }
-                switch (l) {
-                case 0:
-                    row[col] = T(R * Y[0]);
-                    col += 1;
-                    break;
-                case 1:
-                    row[col] = T(R * Y[1]);
-                    row[col + 1] = T(R * Y[2]);
-                    row[col + 2] = T(R * Y[3]);
-                    col += 3;
-                    break;
-                case 2:
-    #pragma unroll
-                    for (int f = 0; f < 5; ++f) row[col + f] = T(R * Y[4 + f]);
-                    col += 5;
-                    break;
-                default:
-    #pragma unroll
-                    for (int f = 0; f < 7; ++f) row[col + f] = T(R * Y[9 + f]);
-                    col += 7;
-                    break;
-                }
             }
-        }
+        };
+        if (staged) pairs(std::true_type{});
+        else pairs(std::false_type{});
         const int pad = u.ld - u.m;
         if (pad > 0) {
-            const int64_t np = (int64_t)u.n_points * pad;
-            for (int64_t q = threadIdx.x; q < np; q += blockDim.x) {
+            const int64_t ne = (int64_t)u.n_points * pad;
+            for (int64_t q = tid; q < ne; q += blockDim.x) {
                 const int64_t pl = q / pad;
                 out[pl * u.ld + u.m + (q - pl * pad)] = T(0);
             }

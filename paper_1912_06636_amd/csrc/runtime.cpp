@@ -1033,6 +1033,8 @@ static nao_status setup_system(nao_system s, const double* xyz, const double* w)
     d.spline = s->d_spline.as<double>();
     d.species_fn_ptr = s->d_fn_ptr.as<int32_t>();
     d.fn_code = s->d_fn_code.as<int32_t>();
+    d.n_species = B.n_species;
+    d.n_shells = B.shell_ptr[B.n_species];
     d.n_radial = B.n_radial;
     d.n_knots = B.n_knots;
     d.n_basis = B.n_basis;
