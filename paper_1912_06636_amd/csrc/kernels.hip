@@ -7,6 +7,7 @@
 //     the 64-wide basis tile, padding columns zero;
 //   - D and H dense row-major [N_b][N_b] FP64; n in the caller's point order.
 #include <algorithm>
+#include <atomic>
 #include <type_traits>
 
 #include <hip/hip_runtime.h>
@@ -103,94 +104,8 @@ __device__ inline void real_ylm(double x, double y, double z, int lmax, double* 
 }
 
 // ------------------------------------------------------------------------------------------
-// Basis evaluation: one workgroup per execution unit; threads over (point, atom) pairs with
-// the atom fastest, each writing all functions of its atom; spline tables staged in LDS.
+// Basis evaluation
 constexpr size_t BASIS_LDS_BYTES = (size_t)MAX_SPLINE_LDS * sizeof(double);
-
-__device__ inline double spline_value(const double* spl, const double* par, int rr, int nk, double d2, double r,
-                                      double lnr)
-{
-    if (!(d2 < par[1])) return 0.0;
-    double t = r > par[0] ? (lnr - par[3]) * par[2] : 0.0;
-    t = fmin(fmax(t, 0.0), (double)(nk - 1));
-    const int k = min((int)t, nk - 2);
-    const double w = t - (double)k;
-    const double* c = spl + ((int64_t)rr * (nk - 1) + k) * 4;
-    return c[0] + w * (c[1] + w * (c[2] + w * c[3]));
-}
-
-// One real spherical harmonic (l <= 3, index l*l + m + l) of a unit vector.
-__device__ inline double ylm_one(int lm, double x, double y, double z)
-{
-    switch (lm) {
-    case 0: return 0.28209479177387814;
-    case 1: return 0.48860251190291992 * y;
-    case 2: return 0.48860251190291992 * z;
-    case 3: return 0.48860251190291992 * x;
-    case 4: return 1.0925484305920792 * x * y;
-    case 5: return 1.0925484305920792 * y * z;
-    case 6: return 0.31539156525252005 * (3.0 * z * z - 1.0);
-    case 7: return 1.0925484305920792 * x * z;
-    case 8: return 0.54627421529603959 * (x * x - y * y);
-    case 9: return 0.59004358992664352 * y * (3.0 * x * x - y * y);
-    case 10: return 2.8906114426405538 * x * y * z;
-    case 11: return 0.45704579946446572 * y * (5.0 * z * z - 1.0);
-    case 12: return 0.37317633259011546 * (5.0 * z * z * z - 3.0 * z);
-    case 13: return 0.45704579946446572 * x * (5.0 * z * z - 1.0);
-    case 14: return 1.4453057213202769 * z * (x * x - y * y);
-    default: return 0.59004358992664352 * x * (x * x - 3.0 * y * y);
-    }
-}
-
-// Columns [c_lo, c_hi) of one atom (its functions start at unit column col_a) at one point;
-// put(c, value) receives every value.
-template <typename Put>
-__device__ inline void eval_atom_cols(const DevSys* __restrict__ S, int atom, double px, double py, double pz,
-                                      int col_a, int c_lo, int c_hi, Put&& put)
-{
-    const double* A = S->atom_xyzr + 4 * (int64_t)atom;
-    const double dx = px - A[0], dy = py - A[1], dz = pz - A[2];
-    const double d2 = dist2_exact(dx, dy, dz);
-    if (!(d2 < A[3])) {
-        for (int c = c_lo; c < c_hi; ++c) put(c, 0.0);
-        return;
-    }
-    const int sp = S->atom_species[atom];
-    const int fptr = S->species_fn_ptr[sp], sh0 = S->species_shell_ptr[sp];
-    const double r = sqrt(d2);
-    double ux = 0.0, uy = 0.0, uz = 1.0, lnr = 0.0;
-    if (r > 0.0) {
-        const double ir = 1.0 / r;
-        ux = dx * ir;
-        uy = dy * ir;
-        uz = dz * ir;
-        lnr = log(r);
-    }
-    const int nk = S->n_knots;
-    int last = -1;
-    double R = 0.0;
-    for (int c = c_lo; c < c_hi; ++c) {
-        const int code = S->fn_code[fptr + (c - col_a)];
-        const int sh = code >> 4;
-        if (sh != last) {
-            const int rr = S->shell_radial[sh0 + sh];
-            R = spline_value(S->spline, S->radial_par + 4 * rr, rr, nk, d2, r, lnr);
-            last = sh;
-        }
-        put(c, R * ylm_one(code & 15, ux, uy, uz));
-    }
-}
-
-// Slot (index into the unit's atom list) of the atom owning unit column col.
-__device__ inline int slot_of(const int32_t* __restrict__ cols, int na, int col)
-{
-    int lo = 0, hi = na - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (cols[mid] <= col) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
 
 constexpr int BASIS_ATOMS = 256;   // atoms of a unit staged in LDS
 constexpr int BASIS_SHELLS = 128;  // shells of a system staged in LDS
@@ -377,8 +292,12 @@ hipError_t launch_basis(const DevSeg* segs_dev, int n_segs, int64_t n_units, int
     const dim3 g(grid_for(n_units, max_grid)), b(256);
     const bool staged = spline_lds > 0;
     const size_t lds = (size_t)spline_lds * sizeof(double);
-    static bool attrs_set = false;  // dynamic LDS above 64 KiB must be allowed per kernel
-    if (!attrs_set) {
+    // dynamic LDS above 64 KiB must be allowed per kernel, once per device
+    static std::atomic<uint64_t> attrs_set{0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return hipErrorInvalidDevice;
+    const uint64_t bit = 1ull << (dev & 63);
+    if (!(attrs_set.load() & bit)) {
         const void* fns[] = {reinterpret_cast<const void*>(&basis_kernel<float, true>),
                              reinterpret_cast<const void*>(&basis_kernel<float, false>),
                              reinterpret_cast<const void*>(&basis_kernel<double, true>),
@@ -387,7 +306,7 @@ hipError_t launch_basis(const DevSeg* segs_dev, int n_segs, int64_t n_units, int
             const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)BASIS_LDS_BYTES);
             if (e != hipSuccess) return e;
         }
-        attrs_set = true;
+        attrs_set.fetch_or(bit);
     }
     if (fp32_out) {
         if (staged) hipLaunchKernelGGL((basis_kernel<float, true>), g, b, lds, st, segs_dev, n_segs, n_units, spline_lds);
@@ -1185,12 +1104,12 @@ hipError_t launch_n(Mode mode, const DevSeg* segs_dev, int n_segs, int64_t n_ite
 {
     if (n_items <= 0 || n_segs <= 0) return hipSuccess;
     if (n_items > 0x7ffffff0) return hipErrorInvalidValue;
-    const dim3 g(grid_for(n_items, max_grid)), b(256);
+    const dim3 g(grid_for(n_items, max_grid)), b(1024);
     switch (mode) {
-    case MODE_FP64: hipLaunchKernelGGL((n_kernel<double, 16, 16, true>), g, dim3(1024), 0, st, segs_dev, n_segs, n_items); break;
-    case MODE_FP32: hipLaunchKernelGGL((n_kernel<float, 16, 16, true>), g, dim3(1024), 0, st, segs_dev, n_segs, n_items); break;
-    case MODE_BF16X3: hipLaunchKernelGGL((n_kernel_bf16<2, 2>), g, dim3(1024), 0, st, segs_dev, n_segs, n_items); break;
-    case MODE_BF16X6: hipLaunchKernelGGL((n_kernel_bf16<3, 1>), g, dim3(1024), 0, st, segs_dev, n_segs, n_items); break;
+    case MODE_FP64: hipLaunchKernelGGL((n_kernel<double, 16, 16, true>), g, b, 0, st, segs_dev, n_segs, n_items); break;
+    case MODE_FP32: hipLaunchKernelGGL((n_kernel<float, 16, 16, true>), g, b, 0, st, segs_dev, n_segs, n_items); break;
+    case MODE_BF16X3: hipLaunchKernelGGL((n_kernel_bf16<2, 2>), g, b, 0, st, segs_dev, n_segs, n_items); break;
+    case MODE_BF16X6: hipLaunchKernelGGL((n_kernel_bf16<3, 1>), g, b, 0, st, segs_dev, n_segs, n_items); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
