@@ -33,9 +33,9 @@ KERNELS_SRC = os.path.join(ROOT, "paper_1912_06636_amd", "csrc", "kernels.hip")
 # --pmc passes (FETCH_SIZE, WRITE_SIZE) over "bench.py --steps 1 --warmup 0 --h-tile 64
 # --no-cpu-baseline --calibrate-copy 1024", each counter scaled by its reading of the 1 GiB
 # plain copy made in that run.  Valid only for the kernel source it was taken on (sha256).
-TRAFFIC = {"sha256": "43b7903e16be0f550b24de811485febd8b6dc54671a12f4d9b51332212aaf17e",
+TRAFFIC = {"sha256": "4df30f16b94cfa297df3b455d8bab92c6d57e5ab512b0530cd35224d5e180c53",
            "workload": "slab375", "precision": "fp64", "h_tile": 64, "group_max": 256,
-           "bytes_per_launch": {"n_f64": 5.970e9, "h_f64": 6.019e9}}
+           "bytes_per_launch": {"n_f64": 5.967e9, "h_f64": 6.019e9}}
 WORKLOADS = {
     "slab375": (4, "375-atom layered slab, 28 NAO/atom (10,500 basis functions, l<=3, 6 A cutoff), "
                    "60x434 grid/atom = 9,765,000 points, octree batches <= 256"),
@@ -170,6 +170,13 @@ def bench_many(args, desc):
     ms_sep = timed(separate, max(1, args.steps // 2))
     value = 2.0 * U / (ms_graph * 1e-3) / 1e9
     log("graph %.2f ms, eager run_many %.2f ms, separate calls %.2f ms" % (ms_graph, ms_eager, ms_sep))
+    for name, fn in (("run_many", lambda: ctx.run_many(work, precision=args.precision, capture_graph=False)),
+                     ("separate", separate)):
+        ctx.profile(True)
+        fn()
+        prof = ctx.profile_read()
+        ctx.profile(False)
+        log("kernels (%s): " % name + ", ".join("%s %d x %.2f ms" % (k, c, t) for k, (c, t) in prof.items()))
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "Gpt·basis²/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_graph, 3), "higher_is_better": True, "scaling": "weak",
