@@ -678,19 +678,25 @@ __global__ __launch_bounds__(64 * NW) void n_kernel(const DevSeg* __restrict__ s
             fetch(0);
             stash(0, 0);
             __syncthreads();
-            for (int c = 0; c < n_chunks; ++c) {
-                const int buf = DB ? (c & 1) : 0;
-                if (c + 1 < n_chunks) fetch(c + 1);
+            auto mfma_chunk = [&](int buf) {
 #pragma unroll
                 for (int kk = 0; kk < KC / 4; ++kk) {
                     const T bv = Bs[buf][kk * 4 + lk][cb * 16 + lr];
 #pragma unroll
                     for (int q = 0; q < R; ++q) acc[q] = M::op(As[buf][(RS * q + rh) * 16 + lr][kk * 4 + lk], bv, acc[q]);
                 }
+            };
+            // straight-line body (the last chunk peeled off) so that the scheduler can
+            // interleave the next chunk's stash with this chunk's MFMAs
+            for (int c = 0; c + 1 < n_chunks; ++c) {
+                const int buf = DB ? (c & 1) : 0;
+                fetch(c + 1);
+                mfma_chunk(buf);
                 if (!DB) __syncthreads();  // every wave is done with the only buffer
-                if (c + 1 < n_chunks) stash(c + 1, DB ? (buf ^ 1) : 0);
+                stash(c + 1, DB ? (buf ^ 1) : 0);
                 __syncthreads();
             }
+            mfma_chunk(DB ? ((n_chunks - 1) & 1) : 0);
 
             // n_p += sum_j T[p][j] Phi[p][j]
             const int cj = J0 + cb * 16 + lr;
