@@ -362,8 +362,10 @@ template <typename T>
 __global__ __launch_bounds__(256, 4) void h_kernel(const DevSeg* __restrict__ segs, int n_segs, int64_t total)
 {
     typedef Mma<T> M;
-    __shared__ T As[2][KCHUNK][TILE + 2];
-    __shared__ T Bs[2][KCHUNK][TILE + 2];
+    constexpr int HK = KCHUNK;              // points per chunk
+    constexpr int HQ = HK * TILE / 256;     // values per thread per chunk and operand
+    __shared__ T As[2][HK][TILE + 2];
+    __shared__ T Bs[2][HK][TILE + 2];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = wave >> 1, wc = wave & 1;
     const int lr = lane & 15, lk = lane >> 4;
@@ -378,18 +380,18 @@ __global__ __launch_bounds__(256, 4) void h_kernel(const DevSeg* __restrict__ se
         gp<const double> __restrict__ wv = gptr(sg.wv + u.point_begin);
         const int np = u.n_points, ld = u.ld;
         const int I0 = it.ti * TILE, J0 = it.tj * TILE;
-        const int n_chunks = (np + KCHUNK - 1) / KCHUNK;
+        const int n_chunks = (np + HK - 1) / HK;
 
         if (np <= 0) continue;
         // Loads are issued unconditionally (rows clamped into the unit) and only consumed at
         // the stash after the next chunk's MFMAs, so that they stay in flight meanwhile.
-        T ra[4], rb[4];
-        double rw[4];
+        T ra[HQ], rb[HQ];
+        double rw[HQ];
         auto fetch = [&](int c) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
+            for (int q = 0; q < HQ; ++q) {
                 const int e = tid + 256 * q;
-                const int pc = min(c * KCHUNK + (e >> 6), np - 1), col = e & 63;
+                const int pc = min(c * HK + (e >> 6), np - 1), col = e & 63;
                 gp<const T> rowp = phi + (int64_t)pc * ld;
                 ra[q] = rowp[I0 + col];
                 rb[q] = rowp[J0 + col];
@@ -398,9 +400,9 @@ __global__ __launch_bounds__(256, 4) void h_kernel(const DevSeg* __restrict__ se
         };
         auto stash = [&](int c, int buf) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
+            for (int q = 0; q < HQ; ++q) {
                 const int e = tid + 256 * q;
-                const bool ok = c * KCHUNK + (e >> 6) < np;
+                const bool ok = c * HK + (e >> 6) < np;
                 As[buf][e >> 6][e & 63] = ok ? T((double)ra[q] * rw[q]) : T(0);
                 Bs[buf][e >> 6][e & 63] = ok ? rb[q] : T(0);
             }
@@ -430,7 +432,7 @@ __global__ __launch_bounds__(256, 4) void h_kernel(const DevSeg* __restrict__ se
                 if (c + 1 < n_chunks) fetch(c + 1);
                 if (decltype(with_mfma)::value) {
 #pragma unroll
-                    for (int kk = 0; kk < KCHUNK / 4; ++kk) {
+                    for (int kk = 0; kk < HK / 4; ++kk) {
                         const int kr = kk * 4 + lk;
                         const T a0 = As[buf][kr][wr * 32 + lr];
                         const T a1 = As[buf][kr][wr * 32 + 16 + lr];
