@@ -216,8 +216,8 @@ nao_status nao_integrate_h(nao_system sys, const double* v, nao_memspace v_space
  * Density n(r_p) = sum_ij phi_i(r_p) D_ij phi_j(r_p) at every point (eq. Density), batch by
  * batch through the batch density matrix D[nnz(B), nnz(B)] (Section "GPGPU Acceleration
  * of the Real-Space Domain Decomposition Algorithm").  D [N_b][N_b] row-major is symmetric;
- * like the symmetric
- * matrix product used for it in the paper, only its upper triangle (i <= j) is read.
+ * like the symmetric matrix product used for it in the paper, only its upper triangle
+ * (i <= j) is read.
  * n [n_points] in caller point order (exact zeros where no basis function reaches).
  * n_electrons (host, nullable) receives N_e = sum_p w_p n_p; passing it synchronizes.
  * ------------------------------------------------------------------------------------- */
