@@ -62,6 +62,7 @@ struct nao_ctx_s {
     int n_cu = 256;
     int64_t persistent_per_cu = 0;       // workgroups per CU of a multi-structure launch (0 = one
                                          // workgroup per item, dispatched by the hardware)
+    std::vector<std::pair<void*, size_t>> spare;  // device buffers of retired launch plans, for reuse
     std::vector<struct ManyPlan*> many;  // launch plans of nao_run_many (captured graphs)
     std::vector<std::pair<hipEvent_t, struct ManyPlan*>> inflight;  // eager plans still running
 };
@@ -177,6 +178,40 @@ nao_status ensure(nao_ctx c, DevArray& a, size_t bytes)
     nao_status s = dev_alloc(c, bytes, &a.p);
     if (s == NAO_OK) a.bytes = bytes;
     return s;
+}
+
+// Launch-plan buffers come from a per-context pool: hipMalloc is slow and hipFree may wait
+// for the whole device, which would stall the work other streams have in flight.
+nao_status pool_take(nao_ctx c, DevArray& a, size_t bytes)
+{
+    bytes = std::max<size_t>(bytes, 256);
+    int best = -1;
+    for (size_t i = 0; i < c->spare.size(); ++i)
+        if (c->spare[i].second >= bytes && (best < 0 || c->spare[i].second < c->spare[best].second)) best = (int)i;
+    if (best >= 0) {
+        a.p = c->spare[best].first;
+        a.bytes = c->spare[best].second;
+        c->spare.erase(c->spare.begin() + best);
+        return NAO_OK;
+    }
+    size_t r = 256;  // powers of two make reuse likely
+    while (r < bytes) r <<= 1;
+    nao_status s = dev_alloc(c, r, &a.p);
+    a.bytes = s == NAO_OK ? r : 0;
+    return s;
+}
+
+// Return a buffer whose work has completed (or is ordered before any later use on the stream).
+void pool_give(nao_ctx c, DevArray& a)
+{
+    if (!a.p) return;
+    c->spare.push_back({a.p, a.bytes});
+    a.p = nullptr;
+    a.bytes = 0;
+    while (c->spare.size() > 32) {
+        dev_free(c, c->spare.front().first, c->spare.front().second);
+        c->spare.erase(c->spare.begin());
+    }
 }
 
 nao_status check_ctx(nao_ctx c)
@@ -431,8 +466,8 @@ void many_free(nao_ctx c, ManyPlan* m)
 {
     if (m->exec) (void)hipGraphExecDestroy(m->exec);
     if (m->graph) (void)hipGraphDestroy(m->graph);
-    dev_free(c, m->d_segs.p, m->d_segs.bytes);
-    dev_free(c, m->d_wv.p, m->d_wv.bytes);
+    pool_give(c, m->d_segs);
+    pool_give(c, m->d_wv);
     delete m;
 }
 
@@ -476,7 +511,7 @@ nao_status many_build(nao_ctx c, const nao_work* work, int64_t n_work, nao_preci
         m->wv_off.push_back(wv_total);
         if (w.op == 0) wv_total += w.sys->n_points;
     }
-    nao_status st = ensure(c, m->d_wv, std::max<int64_t>(1, wv_total) * sizeof(double));
+    nao_status st = pool_take(c, m->d_wv, std::max<int64_t>(1, wv_total) * sizeof(double));
     if (st != NAO_OK) return st;
     // the scratch must hold the largest block of every system (systems may come from other
     // contexts on this device)
@@ -559,9 +594,12 @@ nao_status many_build(nao_ctx c, const nao_work* work, int64_t n_work, nao_preci
         }
         m->chunks.push_back(k);
     }
-    if ((st = upload(c, m->d_segs, m->segs.data(), std::max<size_t>(1, m->segs.size()) * sizeof(DevSeg))) != NAO_OK)
-        return st;
-    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    const size_t seg_bytes = std::max<size_t>(1, m->segs.size()) * sizeof(DevSeg);
+    if ((st = pool_take(c, m->d_segs, seg_bytes)) != NAO_OK) return st;
+    // the host table lives as long as the plan; the copy is ordered before the plan's kernels
+    if (!m->segs.empty())
+        HIP_TRY(c, hipMemcpyAsync(m->d_segs.p, m->segs.data(), m->segs.size() * sizeof(DevSeg), hipMemcpyHostToDevice,
+                                  c->stream));
     return NAO_OK;
 }
 
@@ -768,6 +806,8 @@ void nao_ctx_destroy(nao_ctx c)
     (void)hipSetDevice(c->device);
     many_forget(c, nullptr);
     (void)hipStreamSynchronize(c->stream);
+    for (auto& sp : c->spare) dev_free(c, sp.first, sp.second);
+    c->spare.clear();
     dev_free(c, c->scratch, c->scratch_elems * sizeof(double));
     dev_free(c, c->wsum, (WSUM_BLOCKS + 1) * sizeof(double));
     for (auto& r : c->recs) {
