@@ -33,9 +33,9 @@ KERNELS_SRC = os.path.join(ROOT, "paper_1912_06636_amd", "csrc", "kernels.hip")
 # --pmc passes (FETCH_SIZE, WRITE_SIZE) over "bench.py --steps 1 --warmup 0 --h-tile 64
 # --no-cpu-baseline --calibrate-copy 1024", each counter scaled by its reading of the 1 GiB
 # plain copy made in that run.  Valid only for the kernel source it was taken on (sha256).
-TRAFFIC = {"sha256": "4df30f16b94cfa297df3b455d8bab92c6d57e5ab512b0530cd35224d5e180c53",
+TRAFFIC = {"sha256": "6b2b17a99d23de21f0c0a8de695842f89b509edeb63651655890eef2ba9de5d5",
            "workload": "slab375", "precision": "fp64", "h_tile": 64, "group_max": 256,
-           "bytes_per_launch": {"n_f64": 5.967e9, "h_f64": 6.019e9}}
+           "bytes_per_launch": {"n_f64": 5.961e9, "h_f64": 6.019e9}}
 WORKLOADS = {
     "slab375": (4, "375-atom layered slab, 28 NAO/atom (10,500 basis functions, l<=3, 6 A cutoff), "
                    "60x434 grid/atom = 9,765,000 points, octree batches <= 256"),
