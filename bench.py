@@ -203,6 +203,7 @@ def main():
     ap.add_argument("--group-max", type=int, default=256)
     ap.add_argument("--h-tile", type=int, default=0, help="Hamiltonian tile width (64 or 128); 0 = autotune")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true", help="skip timing the plain FP64 per-batch path")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="MiB copied once by a plain device copy (reference for counter scaling)")
@@ -311,6 +312,30 @@ def main():
                     "launches": launches, "avg_launch_ms": round(tot_ms / launches, 4),
                     "flops_per_launch": credit[dom] / launches}
 
+    # the plain FP64 per-batch path on the same inputs (every octree batch its own unit, FP64),
+    # outside the timed region: the reference the metric's "vs plain FP64" compares with
+    plain = None
+    if not args.no_plain:
+        sysm.set_group_max(0)
+        if h_tile_used != 64:
+            sysm.set_h_tile(64)
+        def plain_step():
+            sysm.update_density(D, precision="fp64", out=n)
+            sysm.integrate_h(v, precision="fp64", out=H)
+        plain_step()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(stream):
+            e0.record(stream)
+            for _ in range(2):
+                plain_step()
+            e1.record(stream)
+        torch.cuda.synchronize()
+        plain_ms = e0.elapsed_time(e1) / 2
+        plain = {"ms_per_step": round(plain_ms, 3), "value": round(2.0 * U / (plain_ms * 1e-3) / 1e9, 3),
+                 "speedup": round(plain_ms / ms_per_step, 3)}
+        log("plain FP64 per-batch path: %.2f ms per step (%.2fx slower)" % (plain_ms, plain_ms / ms_per_step))
+
     cpu = None
     if not args.no_cpu_baseline:
         rate, cores, sdesc = cpu_baseline(work, perm, bp, lp, li, args.cpu_seconds)
@@ -332,6 +357,7 @@ def main():
                        "p99": round(float(np.percentile(step_ms, 99)), 3)},
         "ops_ms": {"density": round(float(np.mean(n_ms)), 3), "hamiltonian": round(float(np.mean(h_ms)), 3)},
         "wall_s_timed": round(t_wall, 3),
+        "plain_fp64_per_batch": plain,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
