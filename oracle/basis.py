@@ -9,13 +9,20 @@ same test that decides batch relevance.  At |r - R_A| = 0 the direction is
 taken as (0, 0, 1).
 
 Global basis order: atom-major, then the species' shell order, then m = -l..l.
+
+Gradient (for the density gradient the paper names beside eq. (Density)): with
+u = (r - R_A)/|r - R_A| and G = dY/du (the harmonic polynomial differentiated in
+the components of u), grad phi = R'(r) u Y + (R/r) (G - u (u . G)), the chain
+rule through du/dr = (I - u u^T)/r.  Reading: grad phi = 0 where phi is zero by
+the cutoff test and for |r - R_A| <= rmin (the clamped, constant part of the
+spline).
 """
 from __future__ import annotations
 
 import numpy as np
 
 from .spline import RadialSpline, evaluate_t, spline_t
-from .ylm import real_ylm
+from .ylm import real_ylm, real_ylm_grad
 
 
 class Basis:
@@ -81,6 +88,40 @@ class Basis:
             R = evaluate_t(spline_t(r, sp.rmin, sp.rcut, sp.n), sp.y, sp.M)
             out[:, c] = np.where(inside, R * Y[:, self.fn_lm[i]], 0.0)
         return out
+
+    def grad_phi_atom(self, pts, a) -> np.ndarray:
+        """grad phi of every basis function of atom a at pts[n, 3] -> [n, nfn(a), 3]."""
+        pts = np.asarray(pts, dtype=np.float64).reshape(-1, 3)
+        X = self.atom_xyz[a]
+        dx = pts[:, 0] - X[0]
+        dy = pts[:, 1] - X[1]
+        dz = pts[:, 2] - X[2]
+        d2 = (dx * dx + dy * dy) + dz * dz
+        r = np.sqrt(d2)
+        safe = np.where(r > 0.0, r, 1.0)
+        u = np.stack([np.where(r > 0.0, dx / safe, 0.0), np.where(r > 0.0, dy / safe, 0.0),
+                      np.where(r > 0.0, dz / safe, 1.0)], axis=1)
+        Y = real_ylm(u)
+        G = real_ylm_grad(u)                                  # [n, 16, 3]
+        Gt = G - u[:, None, :] * np.einsum("nlk,nk->nl", G, u)[:, :, None]  # tangential part
+        fns = range(self.atom_first[a], self.atom_first[a + 1])
+        out = np.zeros((len(pts), len(fns), 3))
+        for c, i in enumerate(fns):
+            sp = self.splines[self.fn_radial[i]]
+            ok = (d2 < sp.rcut * sp.rcut) & (r > sp.rmin)
+            R = evaluate_t(spline_t(r, sp.rmin, sp.rcut, sp.n), sp.y, sp.M)
+            dR = sp.deriv_at_r(r)
+            lm = self.fn_lm[i]
+            g = dR[:, None] * u * Y[:, lm][:, None] + (R / safe)[:, None] * Gt[:, lm, :]
+            out[:, c, :] = np.where(ok[:, None], g, 0.0)
+        return out
+
+    def grad_phi(self, pts, atoms) -> np.ndarray:
+        """grad phi of the functions of `atoms` (ascending) at pts -> [n, m, 3]."""
+        pts = np.asarray(pts, dtype=np.float64).reshape(-1, 3)
+        if len(atoms) == 0:
+            return np.zeros((len(pts), 0, 3))
+        return np.concatenate([self.grad_phi_atom(pts, a) for a in atoms], axis=1)
 
     def phi(self, pts, atoms) -> np.ndarray:
         """phi of the functions of `atoms` (ascending) at pts -> [n, m] in global order."""

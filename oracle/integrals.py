@@ -88,6 +88,45 @@ def density(basis, xyz, D, chunks=None) -> np.ndarray:
     return n
 
 
+def density_gradient(basis, xyz, D, chunks=None):
+    """(n, grad n) at every point: grad n(r_p) = 2 sum_ij grad phi_i(r_p) D_ij phi_j(r_p) for
+    symmetric D (the gradient of eq. Density that the paper names beside it and in the
+    subsection "Density and Density Derivatives, Force and Stress Tensor Components"):
+    T = Phi D, n = rowsum(T * Phi), grad n = 2 rowsum(T * grad Phi) per component."""
+    xyz = np.asarray(xyz, dtype=np.float64).reshape(-1, 3)
+    Ds = symmetric_from_upper(D)
+    n = np.zeros(len(xyz))
+    g = np.zeros((len(xyz), 3))
+    for idx in (chunks if chunks is not None else cell_chunks(xyz)):
+        atoms = relevant_atoms_of_points(xyz[idx], basis.atom_xyz, basis.atom_rcut)
+        if len(atoms) == 0:
+            continue
+        fns = basis.functions_of(atoms)
+        Phi = basis.phi(xyz[idx], atoms)
+        G = basis.grad_phi(xyz[idx], atoms)
+        T = Phi @ Ds[np.ix_(fns, fns)]
+        n[idx] = (T * Phi).sum(axis=1)
+        for k in range(3):
+            g[idx, k] = 2.0 * (T * G[:, :, k]).sum(axis=1)
+    return n, g
+
+
+def density_gradient_at(basis, pts, D) -> np.ndarray:
+    """grad n at selected points, one point at a time (sampled checks at full size)."""
+    pts = np.asarray(pts, dtype=np.float64).reshape(-1, 3)
+    Ds = symmetric_from_upper(D)
+    out = np.zeros((len(pts), 3))
+    for k, p in enumerate(pts):
+        atoms = relevant_atoms_of_points(p[None, :], basis.atom_xyz, basis.atom_rcut)
+        if len(atoms) == 0:
+            continue
+        fns = basis.functions_of(atoms)
+        phi = basis.phi(p[None, :], atoms)[0]
+        G = basis.grad_phi(p[None, :], atoms)[0]
+        out[k] = 2.0 * (G.T @ (Ds[np.ix_(fns, fns)] @ phi))
+    return out
+
+
 def electron_count(w, n) -> float:
     """N_e = sum_p w_p n(r_p)."""
     return float(np.dot(np.asarray(w, dtype=np.float64), np.asarray(n, dtype=np.float64)))

@@ -13,6 +13,11 @@ FHI-aims"); it does not state how they are tabulated.  Reading used here:
   k = min(floor(t), N-2), u = t - k and
   R = (1-u) y_k + u y_{k+1} + (((1-u)^3 - (1-u)) M_k + (u^3 - u) M_{k+1}) / 6.
 
+Radial derivative (for density gradients): dR/dr = (dR/dt) / (r Delta) for
+rmin < r < rcut, with dR/dt the derivative of the evaluation formula in u; the
+spline is constant in the clamped region r <= rmin, so dR/dr = 0 there, and
+dR/dr = 0 at and beyond the cutoff.
+
 Plain Python loops for the tridiagonal solve (Thomas algorithm).
 """
 from __future__ import annotations
@@ -62,6 +67,28 @@ def evaluate_t(t, y, M) -> np.ndarray:
     return a * y[k] + u * y[k + 1] + ((a ** 3 - a) * M[k] + (u ** 3 - u) * M[k + 1]) / 6.0
 
 
+def derivative_t(t, y, M) -> np.ndarray:
+    """dR/dt of the cubic spline at (already clamped) coordinate t."""
+    t = np.asarray(t, dtype=np.float64)
+    n = len(y)
+    k = np.minimum(np.floor(t).astype(np.int64), n - 2)
+    u = t - k
+    a = 1.0 - u
+    # d/du of a y_k + u y_{k+1} + ((a^3 - a) M_k + (u^3 - u) M_{k+1}) / 6, with da/du = -1
+    return (y[k + 1] - y[k]) + ((1.0 - 3.0 * a * a) * M[k] + (3.0 * u * u - 1.0) * M[k + 1]) / 6.0
+
+
+def radial_derivative(r, y, M, rmin: float, rcut: float) -> np.ndarray:
+    """dR/dr: zero for r <= rmin (clamped, constant) and for r >= rcut."""
+    r = np.asarray(r, dtype=np.float64)
+    n = len(y)
+    delta = math.log(rcut / rmin) / (n - 1)
+    inside = (r > rmin) & (r < rcut)
+    safe = np.where(inside, r, 1.0)
+    dt = derivative_t(spline_t(safe, rmin, rcut, n), y, M)
+    return np.where(inside, dt / (safe * delta), 0.0)
+
+
 class RadialSpline:
     """One tabulated radial function R(r) on the logarithmic grid."""
 
@@ -77,3 +104,7 @@ class RadialSpline:
         r = np.asarray(r, dtype=np.float64)
         val = evaluate_t(spline_t(r, self.rmin, self.rcut, self.n), self.y, self.M)
         return np.where(r >= self.rcut, 0.0, val)
+
+    def deriv_at_r(self, r) -> np.ndarray:
+        """dR/dr (zero for r <= rmin and r >= rcut)."""
+        return radial_derivative(r, self.y, self.M, self.rmin, self.rcut)
