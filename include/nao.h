@@ -224,6 +224,21 @@ nao_status nao_integrate_h(nao_system sys, const double* v, nao_memspace v_space
 nao_status nao_update_density(nao_system sys, const double* D, nao_memspace D_space,
                               nao_precision precision, double* n, nao_memspace n_space,
                               double* n_electrons);
+/* ---------------------------------------------------------------------------------------
+ * Density and its gradient at every point, grad n(r_p) = 2 sum_ij grad phi_i(r_p) D_ij phi_j(r_p)
+ * for symmetric D (the density gradients the paper names beside eq. Density and in the
+ * subsection "Density and Density Derivatives, Force and Stress Tensor Components"), batch by
+ * batch: T = Phi D_b over the batch's whole list, n = rowsum(T * Phi), grad n =
+ * 2 rowsum(T * grad Phi).  grad phi = R'(r) u Y + (R / r) (dY/du - u (u . dY/du)) with
+ * u = unit(r - R_A); it is zero where phi is cut off and for |r - R_A| <= rmin (the spline's
+ * clamped, constant part).  D as in nao_update_density (upper triangle read); n [n_points] and
+ * grad_n [n_points][3] in caller point order, both in out_space.  precision: NAO_FP64 or
+ * NAO_FP32 (other values give NAO_ERR_INVALID_ARG).  Needs device scratch for the gradients of
+ * one block of basis values (three times the basis scratch).
+ * ------------------------------------------------------------------------------------- */
+nao_status nao_update_density_gradient(nao_system sys, const double* D, nao_memspace D_space,
+                                       nao_precision precision, double* n, double* grad_n,
+                                       nao_memspace out_space);
 void nao_system_destroy(nao_system sys);
 
 /* ---------------------------------------------------------------------------------------

@@ -103,6 +103,37 @@ __device__ inline void real_ylm(double x, double y, double z, int lmax, double* 
     }
 }
 
+// Partial derivatives of the harmonic polynomials of real_ylm (index lm) with respect to the
+// three components of the unit vector, taken as independent variables.
+__device__ inline void ylm_grad_one(int lm, double x, double y, double z, double* g)
+{
+    const double c1 = 0.48860251190291992, c2a = 1.0925484305920792, c2b = 0.31539156525252005;
+    const double c2c = 0.54627421529603959, c3a = 0.59004358992664352, c3b = 2.8906114426405538;
+    const double c3c = 0.45704579946446572, c3d = 0.37317633259011546, c3e = 1.4453057213202769;
+    double gx = 0.0, gy = 0.0, gz = 0.0;
+    switch (lm) {
+    case 1: gy = c1; break;
+    case 2: gz = c1; break;
+    case 3: gx = c1; break;
+    case 4: gx = c2a * y; gy = c2a * x; break;
+    case 5: gy = c2a * z; gz = c2a * y; break;
+    case 6: gz = 6.0 * c2b * z; break;
+    case 7: gx = c2a * z; gz = c2a * x; break;
+    case 8: gx = 2.0 * c2c * x; gy = -2.0 * c2c * y; break;
+    case 9: gx = 6.0 * c3a * x * y; gy = 3.0 * c3a * (x * x - y * y); break;
+    case 10: gx = c3b * y * z; gy = c3b * x * z; gz = c3b * x * y; break;
+    case 11: gy = c3c * (5.0 * z * z - 1.0); gz = 10.0 * c3c * y * z; break;
+    case 12: gz = c3d * (15.0 * z * z - 3.0); break;
+    case 13: gx = c3c * (5.0 * z * z - 1.0); gz = 10.0 * c3c * x * z; break;
+    case 14: gx = 2.0 * c3e * x * z; gy = -2.0 * c3e * y * z; gz = c3e * (x * x - y * y); break;
+    case 15: gx = 3.0 * c3a * (x * x - y * y); gy = -6.0 * c3a * x * y; break;
+    default: break;
+    }
+    g[0] = gx;
+    g[1] = gy;
+    g[2] = gz;
+}
+
 // ------------------------------------------------------------------------------------------
 // Basis evaluation
 constexpr size_t BASIS_LDS_BYTES = (size_t)MAX_SPLINE_LDS * sizeof(double);
@@ -115,7 +146,7 @@ constexpr int BASIS_SHELLS = 128;  // shells of a system staged in LDS
 // cutoff, species, first column) and the system's shell tables (l, radial function and its
 // parameters) are staged in LDS first, so that a pair's chain of table lookups stays on chip;
 // a unit or system larger than the staging arrays reads them from global memory instead.
-template <typename T, bool SPLINE_LDS>
+template <typename T, bool SPLINE_LDS, bool GRAD>
 __global__ __launch_bounds__(256) void basis_kernel(const DevSeg* __restrict__ segs, int n_segs, int64_t total,
                                                     int spline_lds)
 {
@@ -170,6 +201,8 @@ __global__ __launch_bounds__(256) void basis_kernel(const DevSeg* __restrict__ s
         }
         if (SPLINE_LDS || staged) __syncthreads();
         gp<T> __restrict__ out = gptr(static_cast<T*>(sg.phi) + u.out_offset);
+        // gradients: 3 values per basis value, same element order (GRAD launches only)
+        gp<T> __restrict__ gout = GRAD ? gptr(static_cast<T*>(sg.gphi) + 3 * u.out_offset) : nullptr;
         const int64_t npairs = (int64_t)u.n_points * na;
         const double tmax = (double)(nk - 1);
 
@@ -193,10 +226,13 @@ __global__ __launch_bounds__(256) void basis_kernel(const DevSeg* __restrict__ s
                 const int sh0 = ST ? s_shptr[sp] : shell_ptr[sp];
                 const int sh1 = ST ? s_shptr[sp + 1] : shell_ptr[sp + 1];
                 gp<T> row = out + (int64_t)pl * u.ld;
+                gp<T> grow = GRAD ? gout + 3 * (int64_t)pl * u.ld : nullptr;
                 if (d2 >= arc2) {
                     for (int j = sh0; j < sh1; ++j) {
                         const int nf = 2 * (ST ? s_shell[j][0] : shell_l[j]) + 1;
                         for (int f = 0; f < nf; ++f) row[col + f] = T(0);
+                        if (GRAD)
+                            for (int f = 0; f < 3 * nf; ++f) grow[3 * col + f] = T(0);
                         col += nf;
                     }
                     continue;
@@ -221,19 +257,39 @@ __global__ __launch_bounds__(256) void basis_kernel(const DevSeg* __restrict__ s
                     const double rc2 = ST ? s_par[j][1] : rpar[4 * rr + 1];
                     const double idel = ST ? s_par[j][2] : rpar[4 * rr + 2];
                     const double lnmin = ST ? s_par[j][3] : rpar[4 * rr + 3];
-                    double R = 0.0;
+                    double R = 0.0, dR = 0.0;
                     if (d2 < rc2) {
                         double t = r > rmin ? (lnr - lnmin) * idel : 0.0;
                         t = fmin(fmax(t, 0.0), tmax);
                         const int k = min((int)t, nk - 2);
                         const double w = t - (double)k;
                         const int64_t ci = ((int64_t)rr * (nk - 1) + k) * 4;
+                        double c0, c1, c2, c3;
                         if (SPLINE_LDS) {
-                            const double* c = lds_spline + ci;
-                            R = c[0] + w * (c[1] + w * (c[2] + w * c[3]));
+                            c0 = lds_spline[ci], c1 = lds_spline[ci + 1], c2 = lds_spline[ci + 2], c3 = lds_spline[ci + 3];
                         } else {
                             gp<const double> c = spl + ci;
-                            R = c[0] + w * (c[1] + w * (c[2] + w * c[3]));
+                            c0 = c[0], c1 = c[1], c2 = c[2], c3 = c[3];
+                        }
+                        R = c0 + w * (c1 + w * (c2 + w * c3));
+                        // dR/dr = dR/dw dt/dr with dt/dr = 1 / (r Delta); the clamped part r <= rmin is constant
+                        if (GRAD && r > rmin) dR = (c1 + w * (2.0 * c2 + 3.0 * c3 * w)) * idel / r;
+                    }
+                    if (GRAD) {
+                        // grad phi = R'(r) u Y + (R / r) (G - u (u . G)), G = dY/du; zero where the
+                        // function is cut off or r <= rmin
+                        const bool live = d2 < rc2 && r > rmin;
+                        const double ir = live ? 1.0 / r : 0.0;
+                        for (int f = 0; f < 2 * l + 1; ++f) {
+                            const int lm = l * l + f;
+                            double gv[3];
+                            ylm_grad_one(lm, ux, uy, uz, gv);
+                            const double ug = (ux * gv[0] + uy * gv[1]) + uz * gv[2];
+                            const double yv = Y[lm];
+                            gp<T> dst = grow + 3 * (int64_t)(col + f);
+                            dst[0] = live ? T(dR * ux * yv + R * ir * (gv[0] - ux * ug)) : T(0);
+                            dst[1] = live ? T(dR * uy * yv + R * ir * (gv[1] - uy * ug)) : T(0);
+                            dst[2] = live ? T(dR * uz * yv + R * ir * (gv[2] - uz * ug)) : T(0);
                         }
                     }
                     switch (l) {
@@ -269,6 +325,8 @@ __global__ __launch_bounds__(256) void basis_kernel(const DevSeg* __restrict__ s
             for (int64_t q = tid; q < ne; q += blockDim.x) {
                 const int64_t pl = q / pad;
                 out[pl * u.ld + u.m + (q - pl * pad)] = T(0);
+                if (GRAD)
+                    for (int c = 0; c < 3; ++c) gout[3 * (pl * u.ld + u.m + (q - pl * pad)) + c] = T(0);
             }
         }
     }
@@ -285,7 +343,7 @@ static unsigned grid_for(int64_t n, int64_t max_grid)
 }
 
 hipError_t launch_basis(const DevSeg* segs_dev, int n_segs, int64_t n_units, int spline_lds, bool fp32_out,
-                        hipStream_t st, int64_t max_grid)
+                        hipStream_t st, int64_t max_grid, bool grad)
 {
     if (n_units <= 0 || n_segs <= 0) return hipSuccess;
     if (n_units > 0x7ffffff0 || spline_lds < 0 || spline_lds > MAX_SPLINE_LDS) return hipErrorInvalidValue;
@@ -298,23 +356,33 @@ hipError_t launch_basis(const DevSeg* segs_dev, int n_segs, int64_t n_units, int
     if (hipGetDevice(&dev) != hipSuccess) return hipErrorInvalidDevice;
     const uint64_t bit = 1ull << (dev & 63);
     if (!(attrs_set.load() & bit)) {
-        const void* fns[] = {reinterpret_cast<const void*>(&basis_kernel<float, true>),
-                             reinterpret_cast<const void*>(&basis_kernel<float, false>),
-                             reinterpret_cast<const void*>(&basis_kernel<double, true>),
-                             reinterpret_cast<const void*>(&basis_kernel<double, false>)};
+        const void* fns[] = {reinterpret_cast<const void*>(&basis_kernel<float, true, false>),
+                             reinterpret_cast<const void*>(&basis_kernel<float, false, false>),
+                             reinterpret_cast<const void*>(&basis_kernel<double, true, false>),
+                             reinterpret_cast<const void*>(&basis_kernel<double, false, false>),
+                             reinterpret_cast<const void*>(&basis_kernel<float, true, true>),
+                             reinterpret_cast<const void*>(&basis_kernel<float, false, true>),
+                             reinterpret_cast<const void*>(&basis_kernel<double, true, true>),
+                             reinterpret_cast<const void*>(&basis_kernel<double, false, true>)};
         for (const void* f : fns) {
             const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)BASIS_LDS_BYTES);
             if (e != hipSuccess) return e;
         }
         attrs_set.fetch_or(bit);
     }
+#define NAO_BASIS_LAUNCH(TT, GG)                                                                                 \
+    do {                                                                                                       \
+        if (staged) hipLaunchKernelGGL((basis_kernel<TT, true, GG>), g, b, lds, st, segs_dev, n_segs, n_units, spline_lds); \
+        else hipLaunchKernelGGL((basis_kernel<TT, false, GG>), g, b, lds, st, segs_dev, n_segs, n_units, 0);  \
+    } while (0)
     if (fp32_out) {
-        if (staged) hipLaunchKernelGGL((basis_kernel<float, true>), g, b, lds, st, segs_dev, n_segs, n_units, spline_lds);
-        else hipLaunchKernelGGL((basis_kernel<float, false>), g, b, lds, st, segs_dev, n_segs, n_units, 0);
+        if (grad) NAO_BASIS_LAUNCH(float, true);
+        else NAO_BASIS_LAUNCH(float, false);
     } else {
-        if (staged) hipLaunchKernelGGL((basis_kernel<double, true>), g, b, lds, st, segs_dev, n_segs, n_units, spline_lds);
-        else hipLaunchKernelGGL((basis_kernel<double, false>), g, b, lds, st, segs_dev, n_segs, n_units, 0);
+        if (grad) NAO_BASIS_LAUNCH(double, true);
+        else NAO_BASIS_LAUNCH(double, false);
     }
+#undef NAO_BASIS_LAUNCH
     return hipGetLastError();
 }
 
@@ -586,7 +654,7 @@ __global__ __launch_bounds__(512) void h_kernel_wide(const DevSeg* __restrict__ 
 // chunk is prefetched into registers while the MFMAs of the current one run.  NW waves: wave w
 // owns column block w % 4 and row blocks w / 4, w / 4 + NW / 4, ...  T = FP32 accumulates the
 // whole column tile in FP32; the row dot and the sum over tiles and units are FP64.
-template <typename T, int NW, int KC, bool DB>
+template <typename T, int NW, int KC, bool DB, bool GRAD = false>
 __global__ __launch_bounds__(64 * NW) void n_kernel(const DevSeg* __restrict__ segs, int n_segs, int64_t total)
 {
     typedef Mma<T> M;
@@ -600,7 +668,8 @@ __global__ __launch_bounds__(64 * NW) void n_kernel(const DevSeg* __restrict__ s
                   "tile geometry");
     __shared__ T As[NB][MAX_UNIT_POINTS][KC + 1];
     __shared__ T Bs[NB][KC][TILE + 2];
-    __shared__ double red[4][MAX_UNIT_POINTS];
+    constexpr int NQ = GRAD ? 4 : 1;                         // row dots: n, or n and the three gradient components
+    __shared__ double red[NQ][4][MAX_UNIT_POINTS];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int cb = wave & 3, rh = wave >> 2;  // column block; row blocks rh, rh + RS, ...
     const int lr = lane & 15, lk = lane >> 4;
@@ -619,7 +688,9 @@ __global__ __launch_bounds__(64 * NW) void n_kernel(const DevSeg* __restrict__ s
         if (np <= 0 || m <= 0) continue;
         const int P = (np + 15) >> 4;
         const int J0 = it.tj * TILE;
-        const int n_chunks = (it.tj + 1) * (TILE / KC);      // chunk c covers columns KC c .. KC c + KC - 1
+        // chunk c covers columns KC c .. KC c + KC - 1: the tiles I <= J, or all tiles for the
+        // gradient (T = Phi D over the whole list)
+        const int n_chunks = (GRAD ? (m + TILE - 1) / TILE : it.tj + 1) * (TILE / KC);
         const int cjd = J0 + (tid & (TILE - 1));              // this thread's D column in every chunk
         const int64_t gjd = fn[min(cjd, m - 1)];
 
@@ -650,8 +721,9 @@ __global__ __launch_bounds__(64 * NW) void n_kernel(const DevSeg* __restrict__ s
 #pragma unroll
                 for (int q = 0; q < ND; ++q) {
                     const int ci = KC * c + (tid >> 6) + (NT / TILE) * q;
-                    // upper triangle only: the diagonal tile's lower part is read transposed
-                    const bool lower = diag && ci > cjd;
+                    // upper triangle only: the diagonal tile's lower part (every tile's, for the
+                    // gradient) is read transposed
+                    const bool lower = (GRAD || diag) && ci > cjd;
                     pd[q] = D[lower ? gjd * ldd + gcur[q] : (int64_t)gcur[q] * ldd + gjd];
                 }
                 load_idx(c + 1, gnxt);
@@ -669,7 +741,7 @@ __global__ __launch_bounds__(64 * NW) void n_kernel(const DevSeg* __restrict__ s
                 for (int q = 0; q < ND; ++q) {
                     const int e = tid + NT * q;
                     const bool ok = KC * c + (e >> 6) < m && cjd < m;
-                    Bs[buf][e >> 6][e & 63] = ok ? T(diag ? pd[q] : 2.0 * pd[q]) : T(0);
+                    Bs[buf][e >> 6][e & 63] = ok ? T((GRAD || diag) ? pd[q] : 2.0 * pd[q]) : T(0);
                 }
             };
 
@@ -709,13 +781,19 @@ __global__ __launch_bounds__(64 * NW) void n_kernel(const DevSeg* __restrict__ s
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         const int p = pblk * 16 + M::row(lk, r);
-                        const double f = (double)phi[(int64_t)min(p, np - 1) * ld + cj];
-                        double v = (p < np && cj < m) ? (double)acc[q][r] * f : 0.0;
-                        v += __shfl_xor(v, 1);
-                        v += __shfl_xor(v, 2);
-                        v += __shfl_xor(v, 4);
-                        v += __shfl_xor(v, 8);
-                        if (lr == 0) red[cb][p] = v;
+                        const int64_t e = (int64_t)min(p, np - 1) * ld + cj;
+                        const bool live = p < np && cj < m;
+#pragma unroll
+                        for (int qq = 0; qq < NQ; ++qq) {
+                            const double f = qq == 0 ? (double)phi[e]
+                                                     : (double)gptr(static_cast<const T*>(sg.gphi) + 3 * u.out_offset)[3 * e + qq - 1];
+                            double v = live ? (double)acc[q][r] * f : 0.0;
+                            v += __shfl_xor(v, 1);
+                            v += __shfl_xor(v, 2);
+                            v += __shfl_xor(v, 4);
+                            v += __shfl_xor(v, 8);
+                            if (lr == 0) red[qq][cb][p] = v;
+                        }
                     }
                 }
             }
@@ -735,8 +813,14 @@ __global__ __launch_bounds__(64 * NW) void n_kernel(const DevSeg* __restrict__ s
         }
         __syncthreads();
         if (tid < np) {
-            const double v = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
-            gadd(gptr(sg.n) + gptr(sg.sys->perm)[u.point_begin + tid], v);
+            const int32_t pc = gptr(sg.sys->perm)[u.point_begin + tid];
+            const double v = (red[0][0][tid] + red[0][1][tid]) + (red[0][2][tid] + red[0][3][tid]);
+            gadd(gptr(sg.n) + pc, v);
+            if (GRAD)  // grad n = 2 sum_j T_pj grad phi_pj
+#pragma unroll
+                for (int qq = 1; qq < NQ; ++qq)
+                    gadd(gptr(sg.gn) + 3 * (int64_t)pc + qq - 1,
+                         2.0 * ((red[qq][0][tid] + red[qq][1][tid]) + (red[qq][2][tid] + red[qq][3][tid])));
         }
         __syncthreads();  // red is rewritten by the next item
     }
@@ -1118,6 +1202,19 @@ hipError_t launch_n(Mode mode, const DevSeg* segs_dev, int n_segs, int64_t n_ite
     case MODE_FP32: hipLaunchKernelGGL((n_kernel<float, 16, 16, true>), g, b, 0, st, segs_dev, n_segs, n_items); break;
     case MODE_BF16X3: hipLaunchKernelGGL((n_kernel_bf16<2, 2>), g, b, 0, st, segs_dev, n_segs, n_items); break;
     case MODE_BF16X6: hipLaunchKernelGGL((n_kernel_bf16<3, 1>), g, b, 0, st, segs_dev, n_segs, n_items); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_n_grad(Mode mode, const DevSeg* segs_dev, int n_segs, int64_t n_items, hipStream_t st)
+{
+    if (n_items <= 0 || n_segs <= 0) return hipSuccess;
+    if (n_items > 0x7ffffff0) return hipErrorInvalidValue;
+    const dim3 g(grid_for(n_items, 0)), b(1024);
+    switch (mode) {
+    case MODE_FP64: hipLaunchKernelGGL((n_kernel<double, 16, 16, true, true>), g, b, 0, st, segs_dev, n_segs, n_items); break;
+    case MODE_FP32: hipLaunchKernelGGL((n_kernel<float, 16, 16, true, true>), g, b, 0, st, segs_dev, n_segs, n_items); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -48,6 +48,8 @@ struct nao_ctx_s {
     std::string err;
     double* scratch = nullptr;   // basis values of one block of units
     size_t scratch_elems = 0;
+    void* gscratch = nullptr;    // gradients of the basis values of one block (density gradient)
+    size_t gscratch_bytes = 0;
     size_t scratch_cap_elems = 0;
     double* wsum = nullptr;      // WSUM_BLOCKS partials + 1 result
     int n_systems = 0;
@@ -279,7 +281,7 @@ struct nao_system_s {
     DevArray d_sys, d_px, d_py, d_pz, d_pw, d_perm, d_atoms, d_species, d_shell_ptr, d_shell_l, d_shell_rad,
         d_radial_par, d_spline, d_fn_ptr, d_fn_code;
     DevArray d_units, d_unit_atoms, d_unit_cols, d_unit_fn, d_h_items, d_hw_items, d_n_items;
-    DevArray d_wv, d_v, d_D, d_H, d_n, d_segs;
+    DevArray d_wv, d_v, d_D, d_H, d_n, d_gn, d_segs;
     int spline_lds = 0;  // doubles of spline table staged in LDS by the basis kernel (0 = not staged)
 };
 
@@ -291,7 +293,7 @@ size_t system_bytes(const nao_system_s* s)
                              &s->d_species, &s->d_shell_ptr, &s->d_shell_l, &s->d_shell_rad, &s->d_radial_par,
                              &s->d_spline, &s->d_fn_ptr, &s->d_fn_code, &s->d_units, &s->d_unit_atoms, &s->d_unit_cols, &s->d_unit_fn,
                              &s->d_h_items, &s->d_hw_items, &s->d_n_items, &s->d_wv, &s->d_v, &s->d_D, &s->d_H, &s->d_n,
-                             &s->d_segs};
+                             &s->d_gn, &s->d_segs};
     size_t t = 0;
     for (auto* a : arr) t += a->bytes;
     return t;
@@ -302,7 +304,7 @@ void free_all(nao_system_s* s)
     DevArray* arr[] = {&s->d_sys, &s->d_px, &s->d_py, &s->d_pz, &s->d_pw, &s->d_perm, &s->d_atoms,
                        &s->d_species, &s->d_shell_ptr, &s->d_shell_l, &s->d_shell_rad, &s->d_radial_par,
                        &s->d_spline, &s->d_fn_ptr, &s->d_fn_code, &s->d_units, &s->d_unit_atoms, &s->d_unit_cols, &s->d_unit_fn,
-                       &s->d_h_items, &s->d_hw_items, &s->d_n_items, &s->d_wv, &s->d_v, &s->d_D, &s->d_H, &s->d_n, &s->d_segs};
+                       &s->d_h_items, &s->d_hw_items, &s->d_n_items, &s->d_wv, &s->d_v, &s->d_D, &s->d_H, &s->d_n, &s->d_gn, &s->d_segs};
     for (auto* a : arr) {
         dev_free(s->ctx, a->p, a->bytes);
         a->p = nullptr;
@@ -809,6 +811,7 @@ void nao_ctx_destroy(nao_ctx c)
     for (auto& sp : c->spare) dev_free(c, sp.first, sp.second);
     c->spare.clear();
     dev_free(c, c->scratch, c->scratch_elems * sizeof(double));
+    dev_free(c, c->gscratch, c->gscratch_bytes);
     dev_free(c, c->wsum, (WSUM_BLOCKS + 1) * sizeof(double));
     for (auto& r : c->recs) {
         (void)hipEventDestroy(r.a);
@@ -1402,6 +1405,75 @@ nao_status nao_update_density(nao_system s, const double* D, nao_memspace D_spac
     if (n_space == NAO_MEM_HOST && n > 0)
         HIP_TRY(c, hipMemcpyAsync(nout, nd, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     if (n_space == NAO_MEM_HOST || n_electrons || D_space == NAO_MEM_HOST) HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return NAO_OK;
+}
+
+nao_status nao_update_density_gradient(nao_system s, const double* D, nao_memspace D_space, nao_precision prec,
+                                       double* nout, double* gout, nao_memspace out_space)
+{
+    if (!s) return (g_thread_error = "system is NULL", NAO_ERR_INVALID_ARG);
+    nao_ctx c = s->ctx;
+    nao_status st = check_ctx(c);
+    if (st != NAO_OK) return st;
+    if (prec != NAO_FP64 && prec != NAO_FP32)
+        return (set_err(c, "the density gradient runs in FP64 or FP32"), NAO_ERR_INVALID_ARG);
+    const int64_t n = s->n_points, nb = s->basis.n_basis;
+    if ((nb > 0 && !D) || (n > 0 && (!nout || !gout))) return (set_err(c, "NULL D, n or grad_n"), NAO_ERR_INVALID_ARG);
+    if ((D_space != NAO_MEM_HOST && D_space != NAO_MEM_DEVICE) || (out_space != NAO_MEM_HOST && out_space != NAO_MEM_DEVICE))
+        return (set_err(c, "bad memspace"), NAO_ERR_INVALID_ARG);
+    // gradients of one block's basis values: 3 per value
+    size_t need = 0;
+    for (const Block& b : s->blocks) need = std::max(need, (size_t)b.phi_elems * 3 * sizeof(double));
+    if (need > c->gscratch_bytes) {
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        dev_free(c, c->gscratch, c->gscratch_bytes);
+        c->gscratch = nullptr;
+        c->gscratch_bytes = 0;
+        if ((st = dev_alloc(c, need, &c->gscratch)) != NAO_OK) return st;
+        c->gscratch_bytes = need;
+    }
+    const double* Dd = D;
+    if (D_space == NAO_MEM_HOST && nb > 0) {
+        if ((st = ensure(c, s->d_D, nb * nb * sizeof(double))) != NAO_OK) return st;
+        HIP_TRY(c, hipMemcpyAsync(s->d_D.p, D, nb * nb * sizeof(double), hipMemcpyHostToDevice, c->stream));
+        Dd = s->d_D.as<double>();
+    }
+    double* nd = nout;
+    double* gd = gout;
+    if (out_space == NAO_MEM_HOST) {
+        if ((st = ensure(c, s->d_n, std::max<int64_t>(1, n) * sizeof(double))) != NAO_OK) return st;
+        if ((st = ensure(c, s->d_gn, std::max<int64_t>(1, 3 * n) * sizeof(double))) != NAO_OK) return st;
+        nd = s->d_n.as<double>();
+        gd = s->d_gn.as<double>();
+    }
+    LAUNCH(c, "fill", launch_fill(nd, n, 0.0, c->stream));
+    LAUNCH(c, "fill", launch_fill(gd, 3 * n, 0.0, c->stream));
+    const Mode mode = exec_mode(c, prec);
+    const bool f32 = prec != NAO_FP64;
+    std::vector<DevSeg> segs;
+    for (const Block& b : s->blocks) {
+        DevSeg g = make_seg(s, b, false);
+        g.D = Dd;
+        g.n = nd;
+        g.gn = gd;
+        g.gphi = c->gscratch;
+        segs.push_back(g);
+    }
+    if (!segs.empty()) {
+        HIP_TRY(c, hipMemcpyAsync(s->d_segs.p, segs.data(), segs.size() * sizeof(DevSeg), hipMemcpyHostToDevice,
+                                  c->stream));
+        DevSeg* dseg = s->d_segs.as<DevSeg>();
+        for (size_t k = 0; k < segs.size(); ++k) {
+            LAUNCH(c, f32 ? "basis_grad_f32" : "basis_grad_f64",
+                   launch_basis(dseg + k, 1, segs[k].unit_count, s->spline_lds, f32, c->stream, 0, true));
+            LAUNCH(c, f32 ? "ngrad_f32" : "ngrad_f64", launch_n_grad(mode, dseg + k, 1, segs[k].item_count, c->stream));
+        }
+    }
+    if (out_space == NAO_MEM_HOST && n > 0) {
+        HIP_TRY(c, hipMemcpyAsync(nout, nd, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(gout, gd, 3 * n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    }
+    if (out_space == NAO_MEM_HOST || D_space == NAO_MEM_HOST) HIP_TRY(c, hipStreamSynchronize(c->stream));
     return NAO_OK;
 }
 

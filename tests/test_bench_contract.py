@@ -17,6 +17,9 @@ def test_more_than_one_gpu_exits_with_message():
 
 
 def test_traffic_only_for_the_measured_configuration(monkeypatch):
+    import hashlib
+    with open(bench.KERNELS_SRC, "rb") as f:
+        monkeypatch.setitem(bench.TRAFFIC, "sha256", hashlib.sha256(f.read()).hexdigest())
     t = dict(bench.TRAFFIC)
     ok = bench.measured_traffic(t["workload"], t["precision"], t["h_tile"], t["group_max"], "n_f64")
     assert ok == t["bytes_per_launch"]["n_f64"]
