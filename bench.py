@@ -204,6 +204,7 @@ def main():
     ap.add_argument("--h-tile", type=int, default=0, help="Hamiltonian tile width (64 or 128); 0 = autotune")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip timing the plain FP64 per-batch path")
+    ap.add_argument("--gradient", action="store_true", help="also time the density with its gradient")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="MiB copied once by a plain device copy (reference for counter scaling)")
@@ -336,6 +337,32 @@ def main():
                  "speedup": round(plain_ms / ms_per_step, 3)}
         log("plain FP64 per-batch path: %.2f ms per step (%.2fx slower)" % (plain_ms, plain_ms / ms_per_step))
 
+    grad = None
+    if args.gradient and prec in ("fp64", "fp32"):
+        # density and its gradient (same inputs and grouping as the timed step)
+        sysm.set_group_max(group_max_used)
+        gn = torch.empty((sysm.n_points, 3), dtype=torch.float64, device=dev)
+        sysm.update_density_gradient(D, precision=prec, out=n, out_grad=gn)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(stream):
+            e0.record(stream)
+            for _ in range(2):
+                sysm.update_density_gradient(D, precision=prec, out=n, out_grad=gn)
+            e1.record(stream)
+        torch.cuda.synchronize()
+        g_ms = e0.elapsed_time(e1) / 2
+        ctx.profile(True)
+        sysm.update_density_gradient(D, precision=prec, out=n, out_grad=gn)
+        gprof = ctx.profile_read()
+        ctx.profile(False)
+        grad = {"ms": round(g_ms, 3), "vs_density": round(g_ms / float(np.mean(n_ms)), 3),
+                "gpt_basis2_per_s": round(U / (g_ms * 1e-3) / 1e9, 3),
+                "kernels_ms": {k: round(t, 3) for k, (c, t) in gprof.items()}}
+        log("density + gradient: %.2f ms (%.2fx the density alone); kernels: %s" % (
+            g_ms, g_ms / float(np.mean(n_ms)), grad["kernels_ms"]))
+        del gn
+
     cpu = None
     if not args.no_cpu_baseline:
         rate, cores, sdesc = cpu_baseline(work, perm, bp, lp, li, args.cpu_seconds)
@@ -358,6 +385,7 @@ def main():
         "ops_ms": {"density": round(float(np.mean(n_ms)), 3), "hamiltonian": round(float(np.mean(h_ms)), 3)},
         "wall_s_timed": round(t_wall, 3),
         "plain_fp64_per_batch": plain,
+        "density_gradient": grad,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -125,3 +125,23 @@ def test_reduced_precision_full_size(nao, cfg, prec):
     assert np.all(n[n64 == 0.0] == 0.0)
     tol = FULL_TOL[prec]
     assert eH <= tol and en <= tol and eN <= tol
+
+
+@pytest.mark.parametrize("cfg", [2, 4])
+def test_fp64_gradient_sampled_against_oracle(nao, cfg):
+    say("full-size density gradient vs oracle samples, config", cfg)
+    w, B = full(cfg)
+    _, _, n64, _ = fp64_results(cfg)
+    ctx = nao.Context(0)
+    s = nao.build_batches(ctx, w["basis"], w["xyz"], w["w"], w["max_batch"])
+    n, g = s.update_density_gradient(w["D"])
+    s.close()
+    ctx.close()
+    assert float(np.max(np.abs(n - n64))) <= 1e-12 * float(np.max(np.abs(n64)))
+    gmag = np.abs(g).max(axis=1)
+    rng = np.random.default_rng(40 + cfg)
+    idx = np.concatenate([rng.integers(0, len(n), 96), np.argsort(gmag)[-8:]])
+    gref = oi.density_gradient_at(B, w["xyz"][idx], w["D"])
+    eg = float(np.max(np.abs(g[idx] - gref))) / float(np.max(gmag))
+    say("config", cfg, "sampled e_grad %.3e over %d points" % (eg, len(idx)))
+    assert eg <= 1e-12
