@@ -67,6 +67,31 @@ def hamiltonian(basis, xyz, w, v, chunks=None) -> np.ndarray:
     return 0.5 * (H + H.T)
 
 
+def hamiltonian_gga(basis, xyz, w, v, a, chunks=None) -> np.ndarray:
+    """h_ij = sum_p w_p [v_p phi_i phi_j + a_p . (grad phi_i phi_j + phi_i grad phi_j)] at r_p,
+    the local potential plus a vector field a (for a GGA, a = 2 (df/d sigma) grad n) acting on
+    grad(phi_i phi_j).  Batch form of eq. batch_matrix_mult with K = Phi and
+    L = (w v / 2) Phi + sum_k (w a_k) dPhi/dx_k, so that h = K^T L + L^T K (the symmetric
+    rank-2k product).  a[n_points][3] in caller order."""
+    xyz = np.asarray(xyz, dtype=np.float64).reshape(-1, 3)
+    w = np.asarray(w, dtype=np.float64)
+    wv = w * np.asarray(v, dtype=np.float64)
+    wa = w[:, None] * np.asarray(a, dtype=np.float64).reshape(-1, 3)
+    H = np.zeros((basis.n_basis, basis.n_basis))
+    for idx in (chunks if chunks is not None else cell_chunks(xyz)):
+        atoms = relevant_atoms_of_points(xyz[idx], basis.atom_xyz, basis.atom_rcut)
+        if len(atoms) == 0:
+            continue
+        fns = basis.functions_of(atoms)
+        Phi = basis.phi(xyz[idx], atoms)
+        G = basis.grad_phi(xyz[idx], atoms)
+        L = 0.5 * wv[idx][:, None] * Phi
+        for k in range(3):
+            L = L + wa[idx, k][:, None] * G[:, :, k]
+        H[np.ix_(fns, fns)] += Phi.T @ L + L.T @ Phi
+    return 0.5 * (H + H.T)
+
+
 def overlap(basis, xyz, w, chunks=None) -> np.ndarray:
     """s_ij on the grid: the v = 1 case of the Hamiltonian quadrature."""
     return hamiltonian(basis, xyz, w, np.ones(len(w)), chunks)

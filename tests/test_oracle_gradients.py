@@ -123,3 +123,41 @@ def test_planted_sign_error_in_harmonic_derivative_fails(monkeypatch):
     G = B.grad_phi_atom(pts, 0)
     fd = fd_grad(lambda p: B.phi_atom(p, 0), pts)
     assert np.max(np.abs(G - fd)) > 1e-3 * np.max(np.abs(G))
+
+
+def two_atom_case(seed):
+    xyz = np.array([[0.0, 0.0, 0.0], [1.7, -0.4, 0.6]])
+    basis = g.make_basis(xyz, np.array([0, 0], np.int32), [(0, 1, 2, 3)], [3.5], 11, seed)
+    B = ob.Basis(basis)
+    X, w, _ = g.make_grid(xyz, 3.5, 8, 26)
+    rng = np.random.default_rng(seed)
+    v = rng.normal(size=len(X))
+    a = rng.normal(size=(len(X), 3))
+    return B, X, w, v, a
+
+
+def test_gga_hamiltonian_reduces_to_local_without_field():
+    B, X, w, v, a = two_atom_case(8)
+    H0 = oi.hamiltonian(B, X, w, v)
+    assert np.max(np.abs(oi.hamiltonian_gga(B, X, w, v, np.zeros_like(a)) - H0)) <= 1e-14 * np.max(np.abs(H0))
+
+
+def test_gga_hamiltonian_against_pointwise_loops():
+    """Independent evaluation: for every point and pair (i, j), the integrand
+    w [v phi_i phi_j + a . (grad phi_i phi_j + phi_i grad phi_j)] summed in Python loops."""
+    B, X, w, v, a = two_atom_case(9)
+    idx = np.arange(0, len(X), 7)
+    Xs, ws, vs, as_ = X[idx], w[idx], v[idx], a[idx]
+    H = oi.hamiltonian_gga(B, Xs, ws, vs, as_, chunks=[np.arange(len(Xs))])
+    atoms = np.arange(len(B.atom_xyz))
+    Phi = B.phi(Xs, atoms)
+    G = B.grad_phi(Xs, atoms)
+    nb = B.n_basis
+    ref = np.zeros((nb, nb))
+    for p in range(len(Xs)):
+        for i in range(nb):
+            for j in range(nb):
+                gij = G[p, i] * Phi[p, j] + Phi[p, i] * G[p, j]
+                ref[i, j] += ws[p] * (vs[p] * Phi[p, i] * Phi[p, j] + float(as_[p] @ gij))
+    assert np.max(np.abs(H - ref)) <= 1e-12 * np.max(np.abs(ref))
+    assert np.array_equal(H, H.T)
