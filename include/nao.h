@@ -225,6 +225,19 @@ nao_status nao_update_density(nao_system sys, const double* D, nao_memspace D_sp
                               nao_precision precision, double* n, nao_memspace n_space,
                               double* n_electrons);
 /* ---------------------------------------------------------------------------------------
+ * Hamiltonian with a local potential and a vector field acting on grad(phi_i phi_j),
+ *   H_ij = sum_p w_p [ v_p phi_i phi_j + a_p . (grad phi_i phi_j + phi_i grad phi_j) ]  at r_p,
+ * the form the gradient-dependent part of a GGA potential takes (a = 2 (df/d sigma) grad n);
+ * batch by batch as eq. batch_matrix_mult with K = Phi and L = (w v / 2) Phi + (w a) . grad Phi,
+ * H_b = K^T L + L^T K over the upper-triangle tile pairs.  grad phi as for
+ * nao_update_density_gradient.  v [n_points] and a [n_points][3] in caller point order, both
+ * in in_space; H as for nao_integrate_h.  precision: NAO_FP64 or NAO_FP32.  Needs device scratch
+ * for one L value per basis value of a block (as much as the basis scratch).
+ * ------------------------------------------------------------------------------------- */
+nao_status nao_integrate_h_gga(nao_system sys, const double* v, const double* a, nao_memspace in_space,
+                               nao_precision precision, double* H, nao_memspace H_space);
+
+/* ---------------------------------------------------------------------------------------
  * Density and its gradient at every point, grad n(r_p) = 2 sum_ij grad phi_i(r_p) D_ij phi_j(r_p)
  * for symmetric D (the density gradients the paper names beside eq. Density and in the
  * subsection "Density and Density Derivatives, Force and Stress Tensor Components"), batch by

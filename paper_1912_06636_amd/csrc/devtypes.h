@@ -80,6 +80,7 @@ struct DevSeg {
     void* gphi;              // gradients of the basis values of this block, 3 per value (x, y, z
                              // interleaved; density-gradient launches only)
     double* gn;              // density gradient [n_points][3], caller order
+    const double* wa;        // batch-ordered w*a, 3 per point (Hamiltonian with a vector field)
     int64_t ld;              // n_basis
     int64_t unit_begin, unit_count, unit_prefix;
     int64_t item_begin, item_count, item_prefix;
@@ -96,9 +97,11 @@ enum Mode { MODE_FP64 = 0, MODE_FP32 = 1, MODE_BF16X3 = 2, MODE_BF16X6 = 3 };
 // max_grid > 0 caps the grid: workgroups then loop over the items (persistent launch).
 // spline_lds: doubles of spline table to stage in LDS (0 = read it through the cache); it must
 // cover the largest table of the systems in the segment list.
-// grad: also write the gradient of every basis value to the segments' gphi.
+// extra: also write, to the segments' gphi, the gradient of every basis value (EXTRA_GRAD, 3 per
+// value) or L = (w v / 2) phi + (w a) . grad phi (EXTRA_GGA_L, 1 per value; needs wv and wa).
+enum BasisExtra { EXTRA_NONE = 0, EXTRA_GRAD = 1, EXTRA_GGA_L = 2 };
 hipError_t launch_basis(const DevSeg* segs_dev, int n_segs, int64_t n_units, int spline_lds, bool fp32_out,
-                        hipStream_t st, int64_t max_grid = 0, bool grad = false);
+                        hipStream_t st, int64_t max_grid = 0, int extra = EXTRA_NONE);
 // h_tile: 64, or 128 for the wide FP64/FP32 kernels (items then index 128-wide tiles).
 hipError_t launch_h(Mode mode, const DevSeg* segs_dev, int n_segs, int64_t n_items, hipStream_t st,
                     int64_t max_grid = 0, int h_tile = TILE);
@@ -107,6 +110,11 @@ hipError_t launch_n(Mode mode, const DevSeg* segs_dev, int n_segs, int64_t n_ite
 // Density and its gradient (FP64 or FP32 modes): every item contracts over all of its unit's
 // column tiles, and the row dots take the basis values and their gradients.
 hipError_t launch_n_grad(Mode mode, const DevSeg* segs_dev, int n_segs, int64_t n_items, hipStream_t st);
+// Hamiltonian with a vector field (FP64 or FP32 modes): H[I, J] += Phi_I^T L_J + L_I^T Phi_J over
+// 64-wide tile pairs I <= J, L from the basis launch with EXTRA_GGA_L.
+hipError_t launch_h_gga(Mode mode, const DevSeg* segs_dev, int n_segs, int64_t n_items, hipStream_t st);
+hipError_t launch_wa(const double* pw, const int32_t* perm, const double* a_caller, double* wa, int64_t n_points,
+                     hipStream_t st);
 hipError_t launch_fill(double* p, int64_t n, double value, hipStream_t st);
 hipError_t launch_wv(const double* pw, const int32_t* perm, const double* v_caller, double* wv,
                      int64_t n_points, hipStream_t st);

@@ -146,7 +146,7 @@ constexpr int BASIS_SHELLS = 128;  // shells of a system staged in LDS
 // cutoff, species, first column) and the system's shell tables (l, radial function and its
 // parameters) are staged in LDS first, so that a pair's chain of table lookups stays on chip;
 // a unit or system larger than the staging arrays reads them from global memory instead.
-template <typename T, bool SPLINE_LDS, bool GRAD>
+template <typename T, bool SPLINE_LDS, int EX>
 __global__ __launch_bounds__(256) void basis_kernel(const DevSeg* __restrict__ segs, int n_segs, int64_t total,
                                                     int spline_lds)
 {
@@ -201,8 +201,11 @@ __global__ __launch_bounds__(256) void basis_kernel(const DevSeg* __restrict__ s
         }
         if (SPLINE_LDS || staged) __syncthreads();
         gp<T> __restrict__ out = gptr(static_cast<T*>(sg.phi) + u.out_offset);
-        // gradients: 3 values per basis value, same element order (GRAD launches only)
-        gp<T> __restrict__ gout = GRAD ? gptr(static_cast<T*>(sg.gphi) + 3 * u.out_offset) : nullptr;
+        // EX = EXTRA_GRAD: 3 gradient values per basis value; EX = EXTRA_GGA_L: L = (w v / 2) phi +
+        // (w a) . grad phi, one per basis value; same element order as the basis values
+        constexpr bool GRAD = EX == EXTRA_GRAD, GGA = EX == EXTRA_GGA_L;
+        constexpr int XW = GRAD ? 3 : 1;  // extra values per basis value
+        gp<T> __restrict__ gout = EX != EXTRA_NONE ? gptr(static_cast<T*>(sg.gphi) + XW * u.out_offset) : nullptr;
         const int64_t npairs = (int64_t)u.n_points * na;
         const double tmax = (double)(nk - 1);
 
@@ -226,13 +229,13 @@ __global__ __launch_bounds__(256) void basis_kernel(const DevSeg* __restrict__ s
                 const int sh0 = ST ? s_shptr[sp] : shell_ptr[sp];
                 const int sh1 = ST ? s_shptr[sp + 1] : shell_ptr[sp + 1];
                 gp<T> row = out + (int64_t)pl * u.ld;
-                gp<T> grow = GRAD ? gout + 3 * (int64_t)pl * u.ld : nullptr;
+                gp<T> grow = EX != EXTRA_NONE ? gout + XW * (int64_t)pl * u.ld : nullptr;
                 if (d2 >= arc2) {
                     for (int j = sh0; j < sh1; ++j) {
                         const int nf = 2 * (ST ? s_shell[j][0] : shell_l[j]) + 1;
                         for (int f = 0; f < nf; ++f) row[col + f] = T(0);
-                        if (GRAD)
-                            for (int f = 0; f < 3 * nf; ++f) grow[3 * col + f] = T(0);
+                        if (EX != EXTRA_NONE)
+                            for (int f = 0; f < XW * nf; ++f) grow[XW * col + f] = T(0);
                         col += nf;
                     }
                     continue;
@@ -273,23 +276,36 @@ __global__ __launch_bounds__(256) void basis_kernel(const DevSeg* __restrict__ s
                         }
                         R = c0 + w * (c1 + w * (c2 + w * c3));
                         // dR/dr = dR/dw dt/dr with dt/dr = 1 / (r Delta); the clamped part r <= rmin is constant
-                        if (GRAD && r > rmin) dR = (c1 + w * (2.0 * c2 + 3.0 * c3 * w)) * idel / r;
+                        if (EX != EXTRA_NONE && r > rmin) dR = (c1 + w * (2.0 * c2 + 3.0 * c3 * w)) * idel / r;
                     }
-                    if (GRAD) {
+                    if (EX != EXTRA_NONE) {
                         // grad phi = R'(r) u Y + (R / r) (G - u (u . G)), G = dY/du; zero where the
                         // function is cut off or r <= rmin
                         const bool live = d2 < rc2 && r > rmin;
                         const double ir = live ? 1.0 / r : 0.0;
+                        double hwv = 0.0, wax = 0.0, way = 0.0, waz = 0.0;
+                        if (GGA) {
+                            hwv = 0.5 * gptr(sg.wv)[p];
+                            gp<const double> wa = gptr(sg.wa) + 3 * p;
+                            wax = wa[0], way = wa[1], waz = wa[2];
+                        }
                         for (int f = 0; f < 2 * l + 1; ++f) {
                             const int lm = l * l + f;
                             double gv[3];
                             ylm_grad_one(lm, ux, uy, uz, gv);
                             const double ug = (ux * gv[0] + uy * gv[1]) + uz * gv[2];
                             const double yv = Y[lm];
-                            gp<T> dst = grow + 3 * (int64_t)(col + f);
-                            dst[0] = live ? T(dR * ux * yv + R * ir * (gv[0] - ux * ug)) : T(0);
-                            dst[1] = live ? T(dR * uy * yv + R * ir * (gv[1] - uy * ug)) : T(0);
-                            dst[2] = live ? T(dR * uz * yv + R * ir * (gv[2] - uz * ug)) : T(0);
+                            const double g0 = live ? dR * ux * yv + R * ir * (gv[0] - ux * ug) : 0.0;
+                            const double g1 = live ? dR * uy * yv + R * ir * (gv[1] - uy * ug) : 0.0;
+                            const double g2 = live ? dR * uz * yv + R * ir * (gv[2] - uz * ug) : 0.0;
+                            if (GRAD) {
+                                gp<T> dst = grow + 3 * (int64_t)(col + f);
+                                dst[0] = T(g0);
+                                dst[1] = T(g1);
+                                dst[2] = T(g2);
+                            } else {
+                                grow[col + f] = T(hwv * (R * yv) + ((wax * g0 + way * g1) + waz * g2));
+                            }
                         }
                     }
                     switch (l) {
@@ -325,8 +341,8 @@ __global__ __launch_bounds__(256) void basis_kernel(const DevSeg* __restrict__ s
             for (int64_t q = tid; q < ne; q += blockDim.x) {
                 const int64_t pl = q / pad;
                 out[pl * u.ld + u.m + (q - pl * pad)] = T(0);
-                if (GRAD)
-                    for (int c = 0; c < 3; ++c) gout[3 * (pl * u.ld + u.m + (q - pl * pad)) + c] = T(0);
+                if (EX != EXTRA_NONE)
+                    for (int c = 0; c < XW; ++c) gout[XW * (pl * u.ld + u.m + (q - pl * pad)) + c] = T(0);
             }
         }
     }
@@ -343,10 +359,11 @@ static unsigned grid_for(int64_t n, int64_t max_grid)
 }
 
 hipError_t launch_basis(const DevSeg* segs_dev, int n_segs, int64_t n_units, int spline_lds, bool fp32_out,
-                        hipStream_t st, int64_t max_grid, bool grad)
+                        hipStream_t st, int64_t max_grid, int extra)
 {
     if (n_units <= 0 || n_segs <= 0) return hipSuccess;
     if (n_units > 0x7ffffff0 || spline_lds < 0 || spline_lds > MAX_SPLINE_LDS) return hipErrorInvalidValue;
+    if (extra != EXTRA_NONE && extra != EXTRA_GRAD && extra != EXTRA_GGA_L) return hipErrorInvalidValue;
     const dim3 g(grid_for(n_units, max_grid)), b(256);
     const bool staged = spline_lds > 0;
     const size_t lds = (size_t)spline_lds * sizeof(double);
@@ -356,32 +373,35 @@ hipError_t launch_basis(const DevSeg* segs_dev, int n_segs, int64_t n_units, int
     if (hipGetDevice(&dev) != hipSuccess) return hipErrorInvalidDevice;
     const uint64_t bit = 1ull << (dev & 63);
     if (!(attrs_set.load() & bit)) {
-        const void* fns[] = {reinterpret_cast<const void*>(&basis_kernel<float, true, false>),
-                             reinterpret_cast<const void*>(&basis_kernel<float, false, false>),
-                             reinterpret_cast<const void*>(&basis_kernel<double, true, false>),
-                             reinterpret_cast<const void*>(&basis_kernel<double, false, false>),
-                             reinterpret_cast<const void*>(&basis_kernel<float, true, true>),
-                             reinterpret_cast<const void*>(&basis_kernel<float, false, true>),
-                             reinterpret_cast<const void*>(&basis_kernel<double, true, true>),
-                             reinterpret_cast<const void*>(&basis_kernel<double, false, true>)};
+#define NAO_BASIS_FNS(TT)                                                                                          \
+    reinterpret_cast<const void*>(&basis_kernel<TT, true, EXTRA_NONE>),                                          \
+        reinterpret_cast<const void*>(&basis_kernel<TT, false, EXTRA_NONE>),                                     \
+        reinterpret_cast<const void*>(&basis_kernel<TT, true, EXTRA_GRAD>),                                      \
+        reinterpret_cast<const void*>(&basis_kernel<TT, false, EXTRA_GRAD>),                                     \
+        reinterpret_cast<const void*>(&basis_kernel<TT, true, EXTRA_GGA_L>),                                     \
+        reinterpret_cast<const void*>(&basis_kernel<TT, false, EXTRA_GGA_L>)
+        const void* fns[] = {NAO_BASIS_FNS(float), NAO_BASIS_FNS(double)};
+#undef NAO_BASIS_FNS
         for (const void* f : fns) {
             const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)BASIS_LDS_BYTES);
             if (e != hipSuccess) return e;
         }
         attrs_set.fetch_or(bit);
     }
-#define NAO_BASIS_LAUNCH(TT, GG)                                                                                 \
+#define NAO_BASIS_LAUNCH(TT, EE)                                                                                 \
     do {                                                                                                       \
-        if (staged) hipLaunchKernelGGL((basis_kernel<TT, true, GG>), g, b, lds, st, segs_dev, n_segs, n_units, spline_lds); \
-        else hipLaunchKernelGGL((basis_kernel<TT, false, GG>), g, b, lds, st, segs_dev, n_segs, n_units, 0);  \
+        if (staged) hipLaunchKernelGGL((basis_kernel<TT, true, EE>), g, b, lds, st, segs_dev, n_segs, n_units, spline_lds); \
+        else hipLaunchKernelGGL((basis_kernel<TT, false, EE>), g, b, lds, st, segs_dev, n_segs, n_units, 0);  \
     } while (0)
-    if (fp32_out) {
-        if (grad) NAO_BASIS_LAUNCH(float, true);
-        else NAO_BASIS_LAUNCH(float, false);
-    } else {
-        if (grad) NAO_BASIS_LAUNCH(double, true);
-        else NAO_BASIS_LAUNCH(double, false);
-    }
+#define NAO_BASIS_EXTRA(TT)                                           \
+    do {                                                              \
+        if (extra == EXTRA_GRAD) NAO_BASIS_LAUNCH(TT, EXTRA_GRAD);    \
+        else if (extra == EXTRA_GGA_L) NAO_BASIS_LAUNCH(TT, EXTRA_GGA_L); \
+        else NAO_BASIS_LAUNCH(TT, EXTRA_NONE);                        \
+    } while (0)
+    if (fp32_out) NAO_BASIS_EXTRA(float);
+    else NAO_BASIS_EXTRA(double);
+#undef NAO_BASIS_EXTRA
 #undef NAO_BASIS_LAUNCH
     return hipGetLastError();
 }
@@ -518,6 +538,126 @@ __global__ __launch_bounds__(256, 4) void h_kernel(const DevSeg* __restrict__ se
         };
         const bool diag = it.ti == it.tj;
         if (diag && wr > wc) {
+            k_loop(std::false_type{});
+            continue;
+        }
+        k_loop(std::true_type{});
+
+        gp<double> __restrict__ H = gptr(sg.H);
+        const int64_t ldh = sg.ld;
+#pragma unroll
+        for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+            for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = wr * 32 + ib * 16 + M::row(lk, r);
+                    const int col = wc * 32 + jb * 16 + lr;
+                    const int ci = I0 + row, cj = J0 + col;
+                    if (ci < u.m && cj < u.m && (!diag || row <= col))
+                        gadd(H + (int64_t)gI[ib][r] * ldh + gJ[jb], (double)acc[ib][jb][r]);
+                }
+    }
+}
+
+// Hamiltonian with a vector field (GGA form of eq. batch_matrix_mult): per item one 64x64 tile
+// pair (I <= J) of a unit, H[I, J] += Phi_I^T L_J + L_I^T Phi_J, with L = (w v / 2) Phi +
+// (w a) . grad Phi written by the basis launch.  Same schedule as h_kernel: K = points in
+// double-buffered chunks of 16, four waves of 32x32, FP64 atomics into the upper triangle.
+template <typename T>
+__global__ __launch_bounds__(256, 2) void h_kernel_gga(const DevSeg* __restrict__ segs, int n_segs, int64_t total)
+{
+    typedef Mma<T> M;
+    constexpr int HQ = KCHUNK * TILE / 256;  // values per thread per chunk and operand
+    __shared__ T Ps[2][2][KCHUNK][TILE + 2];  // [buffer][I, J] basis values
+    __shared__ T Ls[2][2][KCHUNK][TILE + 2];  // [buffer][I, J] L values
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = wave >> 1, wc = wave & 1;
+    const int lr = lane & 15, lk = lane >> 4;
+    for (int64_t v_ = blockIdx.x; v_ < xcd_span(total); v_ += gridDim.x) {
+        const int64_t b = xcd_item(v_, total);
+        if (b >= total) continue;
+        const int s = find_segment(segs, n_segs, b, [](const DevSeg& g) { return g.item_prefix; });
+        const DevSeg& sg = segs[s];
+        const HItem it = static_cast<const HItem*>(sg.items)[sg.item_begin + (b - sg.item_prefix)];
+        const DevUnit u = sg.units[it.unit];
+        gp<const T> __restrict__ phi = gptr(static_cast<const T*>(sg.phi) + u.out_offset);
+        gp<const T> __restrict__ lv = gptr(static_cast<const T*>(sg.gphi) + u.out_offset);
+        const int np = u.n_points, ld = u.ld;
+        if (np <= 0) continue;
+        const int I0 = it.ti * TILE, J0 = it.tj * TILE;
+        const int n_chunks = (np + KCHUNK - 1) / KCHUNK;
+
+        T rp[2][HQ], rl[2][HQ];  // [I, J] basis and L values of the next chunk
+        auto fetch = [&](int c) {
+#pragma unroll
+            for (int q = 0; q < HQ; ++q) {
+                const int e = tid + 256 * q;
+                const int64_t o = (int64_t)min(c * KCHUNK + (e >> 6), np - 1) * ld + (e & 63);
+                rp[0][q] = phi[o + I0];
+                rp[1][q] = phi[o + J0];
+                rl[0][q] = lv[o + I0];
+                rl[1][q] = lv[o + J0];
+            }
+        };
+        auto stash = [&](int c, int buf) {
+#pragma unroll
+            for (int q = 0; q < HQ; ++q) {
+                const int e = tid + 256 * q;
+                const bool ok = c * KCHUNK + (e >> 6) < np;
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    Ps[buf][t][e >> 6][e & 63] = ok ? rp[t][q] : T(0);
+                    Ls[buf][t][e >> 6][e & 63] = ok ? rl[t][q] : T(0);
+                }
+            }
+        };
+        gp<const int32_t> __restrict__ fn = gptr(sg.unit_fn + u.fn_begin);
+        int32_t gI[2][4], gJ[2];
+#pragma unroll
+        for (int ib = 0; ib < 2; ++ib) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) gI[ib][r] = fn[min(I0 + wr * 32 + ib * 16 + M::row(lk, r), u.m - 1)];
+            gJ[ib] = fn[min(J0 + wc * 32 + ib * 16 + lr, u.m - 1)];
+        }
+
+        typename M::acc_t acc[2][2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] = M::zero();
+        auto k_loop = [&](auto with_mfma) {
+            fetch(0);
+            stash(0, 0);
+            __syncthreads();
+            for (int c = 0; c < n_chunks; ++c) {
+                const int buf = c & 1;
+                if (c + 1 < n_chunks) fetch(c + 1);
+                if (decltype(with_mfma)::value) {
+#pragma unroll
+                    for (int kk = 0; kk < KCHUNK / 4; ++kk) {
+                        const int kr = kk * 4 + lk;
+                        // Phi_I^T L_J, then L_I^T Phi_J
+                        const T a0 = Ps[buf][0][kr][wr * 32 + lr], a1 = Ps[buf][0][kr][wr * 32 + 16 + lr];
+                        const T b0 = Ls[buf][1][kr][wc * 32 + lr], b1 = Ls[buf][1][kr][wc * 32 + 16 + lr];
+                        acc[0][0] = M::op(a0, b0, acc[0][0]);
+                        acc[0][1] = M::op(a0, b1, acc[0][1]);
+                        acc[1][0] = M::op(a1, b0, acc[1][0]);
+                        acc[1][1] = M::op(a1, b1, acc[1][1]);
+                        const T c0 = Ls[buf][0][kr][wr * 32 + lr], c1 = Ls[buf][0][kr][wr * 32 + 16 + lr];
+                        const T d0 = Ps[buf][1][kr][wc * 32 + lr], d1 = Ps[buf][1][kr][wc * 32 + 16 + lr];
+                        acc[0][0] = M::op(c0, d0, acc[0][0]);
+                        acc[0][1] = M::op(c0, d1, acc[0][1]);
+                        acc[1][0] = M::op(c1, d0, acc[1][0]);
+                        acc[1][1] = M::op(c1, d1, acc[1][1]);
+                    }
+                }
+                if (c + 1 < n_chunks) stash(c + 1, buf ^ 1);
+                __syncthreads();
+            }
+        };
+        const bool diag = it.ti == it.tj;
+        if (diag && wr > wc) {  // the strictly lower quarter of a diagonal tile pair only stages data
             k_loop(std::false_type{});
             continue;
         }
@@ -1220,6 +1360,19 @@ hipError_t launch_n_grad(Mode mode, const DevSeg* segs_dev, int n_segs, int64_t 
     return hipGetLastError();
 }
 
+hipError_t launch_h_gga(Mode mode, const DevSeg* segs_dev, int n_segs, int64_t n_items, hipStream_t st)
+{
+    if (n_items <= 0 || n_segs <= 0) return hipSuccess;
+    if (n_items > 0x7ffffff0) return hipErrorInvalidValue;
+    const dim3 g(grid_for(n_items, 0)), b(256);
+    switch (mode) {
+    case MODE_FP64: hipLaunchKernelGGL(h_kernel_gga<double>, g, b, 0, st, segs_dev, n_segs, n_items); break;
+    case MODE_FP32: hipLaunchKernelGGL(h_kernel_gga<float>, g, b, 0, st, segs_dev, n_segs, n_items); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------------------------------
 // small kernels
 
@@ -1256,6 +1409,24 @@ hipError_t launch_wv(const double* pw, const int32_t* perm, const double* v_call
 }
 
 // H[j][i] = H[i][j] for i < j, through 32x32 LDS tiles (coalesced on both sides).
+__global__ void wa_kernel(const double* __restrict__ pw, const int32_t* __restrict__ perm,
+                          const double* __restrict__ a, double* __restrict__ wa, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 3 * n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p = i / 3;
+        wa[i] = pw[p] * a[3 * (int64_t)perm[p] + (i - 3 * p)];
+    }
+}
+
+hipError_t launch_wa(const double* pw, const int32_t* perm, const double* a_caller, double* wa, int64_t n_points,
+                     hipStream_t st)
+{
+    if (n_points <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((3 * n_points + 255) / 256, 65536);
+    hipLaunchKernelGGL(wa_kernel, dim3((unsigned)blocks), dim3(256), 0, st, pw, perm, a_caller, wa, n_points);
+    return hipGetLastError();
+}
+
 __global__ __launch_bounds__(256) void mirror_kernel(double* __restrict__ H, int64_t n)
 {
     __shared__ double t[32][33];

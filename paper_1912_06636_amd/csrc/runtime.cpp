@@ -281,7 +281,7 @@ struct nao_system_s {
     DevArray d_sys, d_px, d_py, d_pz, d_pw, d_perm, d_atoms, d_species, d_shell_ptr, d_shell_l, d_shell_rad,
         d_radial_par, d_spline, d_fn_ptr, d_fn_code;
     DevArray d_units, d_unit_atoms, d_unit_cols, d_unit_fn, d_h_items, d_hw_items, d_n_items;
-    DevArray d_wv, d_v, d_D, d_H, d_n, d_gn, d_segs;
+    DevArray d_wv, d_v, d_D, d_H, d_n, d_gn, d_a, d_wa, d_segs;
     int spline_lds = 0;  // doubles of spline table staged in LDS by the basis kernel (0 = not staged)
 };
 
@@ -293,7 +293,7 @@ size_t system_bytes(const nao_system_s* s)
                              &s->d_species, &s->d_shell_ptr, &s->d_shell_l, &s->d_shell_rad, &s->d_radial_par,
                              &s->d_spline, &s->d_fn_ptr, &s->d_fn_code, &s->d_units, &s->d_unit_atoms, &s->d_unit_cols, &s->d_unit_fn,
                              &s->d_h_items, &s->d_hw_items, &s->d_n_items, &s->d_wv, &s->d_v, &s->d_D, &s->d_H, &s->d_n,
-                             &s->d_gn, &s->d_segs};
+                             &s->d_gn, &s->d_a, &s->d_wa, &s->d_segs};
     size_t t = 0;
     for (auto* a : arr) t += a->bytes;
     return t;
@@ -304,7 +304,7 @@ void free_all(nao_system_s* s)
     DevArray* arr[] = {&s->d_sys, &s->d_px, &s->d_py, &s->d_pz, &s->d_pw, &s->d_perm, &s->d_atoms,
                        &s->d_species, &s->d_shell_ptr, &s->d_shell_l, &s->d_shell_rad, &s->d_radial_par,
                        &s->d_spline, &s->d_fn_ptr, &s->d_fn_code, &s->d_units, &s->d_unit_atoms, &s->d_unit_cols, &s->d_unit_fn,
-                       &s->d_h_items, &s->d_hw_items, &s->d_n_items, &s->d_wv, &s->d_v, &s->d_D, &s->d_H, &s->d_n, &s->d_gn, &s->d_segs};
+                       &s->d_h_items, &s->d_hw_items, &s->d_n_items, &s->d_wv, &s->d_v, &s->d_D, &s->d_H, &s->d_n, &s->d_gn, &s->d_a, &s->d_wa, &s->d_segs};
     for (auto* a : arr) {
         dev_free(s->ctx, a->p, a->bytes);
         a->p = nullptr;
@@ -1408,6 +1408,85 @@ nao_status nao_update_density(nao_system s, const double* D, nao_memspace D_spac
     return NAO_OK;
 }
 
+// Extra per-block scratch beside the basis values: `per_value` FP64 slots per basis value.
+static nao_status ensure_gscratch(nao_system s, int per_value)
+{
+    nao_ctx c = s->ctx;
+    size_t need = 0;
+    for (const Block& b : s->blocks) need = std::max(need, (size_t)b.phi_elems * per_value * sizeof(double));
+    if (need <= c->gscratch_bytes) return NAO_OK;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    dev_free(c, c->gscratch, c->gscratch_bytes);
+    c->gscratch = nullptr;
+    c->gscratch_bytes = 0;
+    nao_status st = dev_alloc(c, need, &c->gscratch);
+    if (st == NAO_OK) c->gscratch_bytes = need;
+    return st;
+}
+
+nao_status nao_integrate_h_gga(nao_system s, const double* v, const double* a, nao_memspace in_space,
+                               nao_precision prec, double* H, nao_memspace H_space)
+{
+    if (!s) return (g_thread_error = "system is NULL", NAO_ERR_INVALID_ARG);
+    nao_ctx c = s->ctx;
+    nao_status st = check_ctx(c);
+    if (st != NAO_OK) return st;
+    if (prec != NAO_FP64 && prec != NAO_FP32)
+        return (set_err(c, "the Hamiltonian with a vector field runs in FP64 or FP32"), NAO_ERR_INVALID_ARG);
+    const int64_t n = s->n_points, nb = s->basis.n_basis;
+    if (!H || (n > 0 && (!v || !a))) return (set_err(c, "NULL v, a or H"), NAO_ERR_INVALID_ARG);
+    if ((in_space != NAO_MEM_HOST && in_space != NAO_MEM_DEVICE) || (H_space != NAO_MEM_HOST && H_space != NAO_MEM_DEVICE))
+        return (set_err(c, "bad memspace"), NAO_ERR_INVALID_ARG);
+    if ((st = ensure_gscratch(s, 1)) != NAO_OK) return st;  // L: one value per basis value
+    const double* vd = v;
+    const double* ad = a;
+    if (in_space == NAO_MEM_HOST && n > 0) {
+        if ((st = ensure(c, s->d_v, n * sizeof(double))) != NAO_OK) return st;
+        if ((st = ensure(c, s->d_a, 3 * n * sizeof(double))) != NAO_OK) return st;
+        HIP_TRY(c, hipMemcpyAsync(s->d_v.p, v, n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(s->d_a.p, a, 3 * n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+        vd = s->d_v.as<double>();
+        ad = s->d_a.as<double>();
+    }
+    if ((st = ensure(c, s->d_wa, std::max<int64_t>(1, 3 * n) * sizeof(double))) != NAO_OK) return st;
+    double* Hd = H;
+    if (H_space == NAO_MEM_HOST) {
+        if ((st = ensure(c, s->d_H, std::max<int64_t>(1, nb * nb) * sizeof(double))) != NAO_OK) return st;
+        Hd = s->d_H.as<double>();
+    }
+    LAUNCH(c, "fill", launch_fill(Hd, nb * nb, 0.0, c->stream));
+    LAUNCH(c, "wv", launch_wv(s->d_pw.as<double>(), s->d_perm.as<int32_t>(), vd, s->d_wv.as<double>(), n, c->stream));
+    LAUNCH(c, "wa", launch_wa(s->d_pw.as<double>(), s->d_perm.as<int32_t>(), ad, s->d_wa.as<double>(), n, c->stream));
+    const Mode mode = exec_mode(c, prec);
+    const bool f32 = prec != NAO_FP64;
+    std::vector<DevSeg> segs;
+    for (const Block& b : s->blocks) {
+        DevSeg g = make_seg(s, b, true, false);
+        g.wv = s->d_wv.as<double>();
+        g.wa = s->d_wa.as<double>();
+        g.H = Hd;
+        g.gphi = c->gscratch;
+        segs.push_back(g);
+    }
+    if (!segs.empty()) {
+        HIP_TRY(c, hipMemcpyAsync(s->d_segs.p, segs.data(), segs.size() * sizeof(DevSeg), hipMemcpyHostToDevice,
+                                  c->stream));
+        DevSeg* dseg = s->d_segs.as<DevSeg>();
+        for (size_t k = 0; k < segs.size(); ++k) {
+            LAUNCH(c, f32 ? "basis_gga_f32" : "basis_gga_f64",
+                   launch_basis(dseg + k, 1, segs[k].unit_count, s->spline_lds, f32, c->stream, 0, EXTRA_GGA_L));
+            LAUNCH(c, f32 ? "hgga_f32" : "hgga_f64", launch_h_gga(mode, dseg + k, 1, segs[k].item_count, c->stream));
+        }
+    }
+    LAUNCH(c, "mirror", launch_mirror(Hd, nb, c->stream));
+    if (H_space == NAO_MEM_HOST) {
+        HIP_TRY(c, hipMemcpyAsync(H, Hd, nb * nb * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+    }
+    if (in_space == NAO_MEM_HOST) HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return NAO_OK;
+}
+
 nao_status nao_update_density_gradient(nao_system s, const double* D, nao_memspace D_space, nao_precision prec,
                                        double* nout, double* gout, nao_memspace out_space)
 {
@@ -1422,16 +1501,7 @@ nao_status nao_update_density_gradient(nao_system s, const double* D, nao_memspa
     if ((D_space != NAO_MEM_HOST && D_space != NAO_MEM_DEVICE) || (out_space != NAO_MEM_HOST && out_space != NAO_MEM_DEVICE))
         return (set_err(c, "bad memspace"), NAO_ERR_INVALID_ARG);
     // gradients of one block's basis values: 3 per value
-    size_t need = 0;
-    for (const Block& b : s->blocks) need = std::max(need, (size_t)b.phi_elems * 3 * sizeof(double));
-    if (need > c->gscratch_bytes) {
-        HIP_TRY(c, hipStreamSynchronize(c->stream));
-        dev_free(c, c->gscratch, c->gscratch_bytes);
-        c->gscratch = nullptr;
-        c->gscratch_bytes = 0;
-        if ((st = dev_alloc(c, need, &c->gscratch)) != NAO_OK) return st;
-        c->gscratch_bytes = need;
-    }
+    if ((st = ensure_gscratch(s, 3)) != NAO_OK) return st;
     const double* Dd = D;
     if (D_space == NAO_MEM_HOST && nb > 0) {
         if ((st = ensure(c, s->d_D, nb * nb * sizeof(double))) != NAO_OK) return st;
@@ -1465,7 +1535,7 @@ nao_status nao_update_density_gradient(nao_system s, const double* D, nao_memspa
         DevSeg* dseg = s->d_segs.as<DevSeg>();
         for (size_t k = 0; k < segs.size(); ++k) {
             LAUNCH(c, f32 ? "basis_grad_f32" : "basis_grad_f64",
-                   launch_basis(dseg + k, 1, segs[k].unit_count, s->spline_lds, f32, c->stream, 0, true));
+                   launch_basis(dseg + k, 1, segs[k].unit_count, s->spline_lds, f32, c->stream, 0, EXTRA_GRAD));
             LAUNCH(c, f32 ? "ngrad_f32" : "ngrad_f64", launch_n_grad(mode, dseg + k, 1, segs[k].item_count, c->stream));
         }
     }

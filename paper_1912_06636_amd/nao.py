@@ -84,6 +84,7 @@ _sig("nao_eval_basis", _S, _vp, ctypes.c_int64, ctypes.c_int64, _vp, ctypes.c_in
 _sig("nao_integrate_h", _S, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int)
 _sig("nao_update_density", _S, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int, _c_dp)
 _sig("nao_update_density_gradient", _S, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_int)
+_sig("nao_integrate_h_gga", _S, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int)
 _sig("nao_system_destroy", None, _vp)
 _sig("nao_run_many", _S, _vp, ctypes.POINTER(Work), ctypes.c_int64, ctypes.c_int, ctypes.c_uint32)
 _sig("nao_server_create", _S, _vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int, ctypes.POINTER(_vp))
@@ -102,7 +103,8 @@ EXPORTED = [
     "nao_ctx_create", "nao_ctx_destroy", "nao_last_error", "nao_ctx_set_stream", "nao_ctx_stream",
     "nao_ctx_synchronize", "nao_ctx_memory", "nao_ctx_profile", "nao_ctx_profile_read", "nao_plan_create", "nao_plan_info", "nao_plan_get_batches",
     "nao_plan_destroy", "nao_build_batches", "nao_system_set_group_max", "nao_system_set_h_tile", "nao_system_autotune", "nao_system_info", "nao_get_batches",
-    "nao_system_work", "nao_eval_basis", "nao_integrate_h", "nao_update_density", "nao_update_density_gradient", "nao_system_destroy",
+    "nao_system_work", "nao_eval_basis", "nao_integrate_h", "nao_update_density", "nao_update_density_gradient", "nao_integrate_h_gga",
+    "nao_system_destroy",
     "nao_run_many", "nao_server_create", "nao_server_open_session", "nao_server_close_session",
     "nao_server_session_info", "nao_server_submit", "nao_server_step", "nao_server_poll", "nao_server_result",
     "nao_server_destroy",
@@ -368,6 +370,18 @@ class System:
         _check(_lib.nao_update_density(self.handle, pd, sd, PRECISIONS[precision], pn, sn,
                                        ctypes.byref(ne) if electrons else None), self.ctx.handle)
         return (out, ne.value) if electrons else out
+
+    def integrate_h_gga(self, v, a, precision="fp64", out=None):
+        """nao_integrate_h_gga: H with the local potential v and the vector field a [n_points, 3]."""
+        pv, sv, kv = _ptr_space(v)
+        pa, sa, ka = _ptr_space(a)
+        if sv != sa:
+            raise ValueError("v and a must be in the same memory space")
+        if out is None:
+            out = np.empty((self.n_basis, self.n_basis), np.float64)
+        ph, sh, kh = _ptr_space(out)
+        _check(_lib.nao_integrate_h_gga(self.handle, pv, pa, sv, PRECISIONS[precision], ph, sh), self.ctx.handle)
+        return out
 
     def update_density_gradient(self, D, precision="fp64", out=None, out_grad=None):
         """nao_update_density_gradient: (n, grad n [n_points, 3]); outputs share a memory space."""

@@ -96,3 +96,47 @@ def test_gradient_device_memspace_and_errors(nao, ctx):
     with pytest.raises(nao.NaoError):
         s.update_density_gradient(w["D"], precision="bf16x3")
     s.close()
+
+
+def field(name, n):
+    """Seeded vector field a [n, 3] (input of the Hamiltonian with a vector field)."""
+    seed = {"config1": 1, "multitile": 2, "two_species": 3}[name]
+    return 0.3 * np.random.default_rng(500 + seed).normal(size=(n, 3))
+
+
+@functools.lru_cache(maxsize=None)
+def ref_gga(name):
+    w, B, ref = case(name)
+    return oi.hamiltonian_gga(B, w["xyz"], w["w"], w["v"], field(name, len(w["xyz"])))
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_gga_hamiltonian_fp64_matches_oracle(nao, ctx, name):
+    w, B, ref = case(name)
+    say("gga hamiltonian fp64", name)
+    a = field(name, len(w["xyz"]))
+    s = nao.build_batches(ctx, w["basis"], w["xyz"], w["w"], w["max_batch"])
+    H = s.integrate_h_gga(w["v"], a)
+    e = rel_max(H, ref_gga(name))
+    say("gga hamiltonian fp64", name, "e_H %.3e" % e)
+    assert e <= 1e-12
+    assert np.array_equal(H, H.T)
+    # without the field it is the local Hamiltonian
+    assert rel_max(s.integrate_h_gga(w["v"], np.zeros_like(a)), ref["H"]) <= 1e-12
+    s.close()
+
+
+def test_gga_hamiltonian_grouping_and_fp32(nao, ctx):
+    w, B, ref = case("multitile")
+    a = field("multitile", len(w["xyz"]))
+    s = nao.build_batches(ctx, w["basis"], w["xyz"], w["w"], w["max_batch"])
+    H0 = s.integrate_h_gga(w["v"], a)
+    s.set_group_max(0)
+    assert rel_max(s.integrate_h_gga(w["v"], a), H0) <= 1e-13
+    s.set_group_max(256)
+    e32 = rel_max(s.integrate_h_gga(w["v"], a, precision="fp32"), ref_gga("multitile"))
+    say("gga hamiltonian fp32 multitile e_H %.3e" % e32)
+    assert e32 <= 1e-5
+    with pytest.raises(nao.NaoError):
+        s.integrate_h_gga(w["v"], a, precision="bf16x6")
+    s.close()
