@@ -92,6 +92,35 @@ def hamiltonian_gga(basis, xyz, w, v, a, chunks=None) -> np.ndarray:
     return 0.5 * (H + H.T)
 
 
+def hamiltonian_gga_entries(basis, xyz, w, v, a, pairs) -> np.ndarray:
+    """hamiltonian_gga's h_ij for selected (i, j) pairs: sum over the points inside both
+    cutoff spheres (sampled checks at full size)."""
+    xyz = np.asarray(xyz, dtype=np.float64).reshape(-1, 3)
+    w = np.asarray(w, dtype=np.float64)
+    wv = w * np.asarray(v, dtype=np.float64)
+    wa = w[:, None] * np.asarray(a, dtype=np.float64).reshape(-1, 3)
+    out = np.zeros(len(pairs))
+    for k, (i, j) in enumerate(pairs):
+        fa, fb = int(basis.fn_atom[i]), int(basis.fn_atom[j])
+        sel = np.ones(len(xyz), dtype=bool)
+        for at in (fa, fb):
+            X = basis.atom_xyz[at]
+            dx = xyz[:, 0] - X[0]
+            dy = xyz[:, 1] - X[1]
+            dz = xyz[:, 2] - X[2]
+            sel &= ((dx * dx + dy * dy) + dz * dz) < basis.atom_rcut[at] * basis.atom_rcut[at]
+        idx = np.nonzero(sel)[0]
+        if len(idx) == 0:
+            continue
+        pa = basis.phi_atom(xyz[idx], fa)[:, i - basis.atom_first[fa]]
+        pb = basis.phi_atom(xyz[idx], fb)[:, j - basis.atom_first[fb]]
+        ga = basis.grad_phi_atom(xyz[idx], fa)[:, i - basis.atom_first[fa], :]
+        gb = basis.grad_phi_atom(xyz[idx], fb)[:, j - basis.atom_first[fb], :]
+        grad_prod = ga * pb[:, None] + pa[:, None] * gb
+        out[k] = float(np.sum(wv[idx] * pa * pb) + np.sum(wa[idx] * grad_prod))
+    return out
+
+
 def overlap(basis, xyz, w, chunks=None) -> np.ndarray:
     """s_ij on the grid: the v = 1 case of the Hamiltonian quadrature."""
     return hamiltonian(basis, xyz, w, np.ones(len(w)), chunks)

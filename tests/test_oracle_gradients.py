@@ -161,3 +161,13 @@ def test_gga_hamiltonian_against_pointwise_loops():
                 ref[i, j] += ws[p] * (vs[p] * Phi[p, i] * Phi[p, j] + float(as_[p] @ gij))
     assert np.max(np.abs(H - ref)) <= 1e-12 * np.max(np.abs(ref))
     assert np.array_equal(H, H.T)
+
+
+def test_gga_entries_equal_full_matrix():
+    B, X, w, v, a = two_atom_case(10)
+    H = oi.hamiltonian_gga(B, X, w, v, a)
+    rng = np.random.default_rng(11)
+    pairs = [(int(i), int(j)) for i, j in rng.integers(0, B.n_basis, (20, 2))]
+    got = oi.hamiltonian_gga_entries(B, X, w, v, a, pairs)
+    ref = np.array([H[i, j] for i, j in pairs])
+    assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(H))
