@@ -362,6 +362,26 @@ def main():
         log("density + gradient: %.2f ms (%.2fx the density alone); kernels: %s" % (
             g_ms, g_ms / float(np.mean(n_ms)), grad["kernels_ms"]))
         del gn
+        # Hamiltonian with a seeded vector field (the GGA term)
+        a = torch.from_numpy(0.3 * np.random.default_rng(99).normal(size=(sysm.n_points, 3))).to(dev)
+        sysm.integrate_h_gga(v, a, precision=prec, out=H)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            e0.record(stream)
+            for _ in range(2):
+                sysm.integrate_h_gga(v, a, precision=prec, out=H)
+            e1.record(stream)
+        torch.cuda.synchronize()
+        gg_ms = e0.elapsed_time(e1) / 2
+        ctx.profile(True)
+        sysm.integrate_h_gga(v, a, precision=prec, out=H)
+        ggprof = ctx.profile_read()
+        ctx.profile(False)
+        grad["hamiltonian_with_field"] = {"ms": round(gg_ms, 3), "vs_hamiltonian": round(gg_ms / float(np.mean(h_ms)), 3),
+                                          "kernels_ms": {k: round(t, 3) for k, (c, t) in ggprof.items()}}
+        log("hamiltonian with a vector field: %.2f ms (%.2fx the local one); kernels: %s" % (
+            gg_ms, gg_ms / float(np.mean(h_ms)), grad["hamiltonian_with_field"]["kernels_ms"]))
+        del a
 
     cpu = None
     if not args.no_cpu_baseline:

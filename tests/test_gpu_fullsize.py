@@ -145,3 +145,22 @@ def test_fp64_gradient_sampled_against_oracle(nao, cfg):
     eg = float(np.max(np.abs(g[idx] - gref))) / float(np.max(gmag))
     say("config", cfg, "sampled e_grad %.3e over %d points" % (eg, len(idx)))
     assert eg <= 1e-12
+
+
+@pytest.mark.parametrize("cfg", [2, 4])
+def test_fp64_gga_hamiltonian_sampled_against_oracle(nao, cfg):
+    say("full-size hamiltonian with a vector field vs oracle samples, config", cfg)
+    w, B = full(cfg)
+    a = 0.3 * np.random.default_rng(60 + cfg).normal(size=(len(w["xyz"]), 3))
+    ctx = nao.Context(0)
+    s = nao.build_batches(ctx, w["basis"], w["xyz"], w["w"], w["max_batch"])
+    H = s.integrate_h_gga(w["v"], a)
+    s.close()
+    ctx.close()
+    assert np.array_equal(H, H.T)
+    pairs = sample_pairs(H, 10, 70 + cfg)
+    ref = oi.hamiltonian_gga_entries(B, w["xyz"], w["w"], w["v"], a, pairs)
+    got = np.array([H[i, j] for i, j in pairs])
+    e = float(np.max(np.abs(got - ref))) / float(np.max(np.abs(H)))
+    say("config", cfg, "sampled e_H %.3e over %d pairs" % (e, len(pairs)))
+    assert e <= 1e-12
