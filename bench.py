@@ -204,7 +204,9 @@ def main():
     ap.add_argument("--h-tile", type=int, default=0, help="Hamiltonian tile width (64 or 128); 0 = autotune")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip timing the plain FP64 per-batch path")
-    ap.add_argument("--gradient", action="store_true", help="also time the density with its gradient")
+    ap.add_argument("--gradient", action="store_true",
+                    help="also time the gradient operations: the density with its gradient, the Hamiltonian "
+                         "with a vector field and the local Pulay forces")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="MiB copied once by a plain device copy (reference for counter scaling)")
@@ -382,6 +384,28 @@ def main():
         log("hamiltonian with a vector field: %.2f ms (%.2fx the local one); kernels: %s" % (
             gg_ms, gg_ms / float(np.mean(h_ms)), grad["hamiltonian_with_field"]["kernels_ms"]))
         del a
+        # local Pulay forces with a seeded energy-weighted density matrix
+        from workloads.generate import energy_weighted_for
+        Q = torch.from_numpy(energy_weighted_for(work, 1)).to(dev)
+        F = torch.empty((sysm.n_atoms, 3), dtype=torch.float64, device=dev)
+        sysm.pulay_forces(D, Q, v, precision=prec, out=F)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            e0.record(stream)
+            for _ in range(2):
+                sysm.pulay_forces(D, Q, v, precision=prec, out=F)
+            e1.record(stream)
+        torch.cuda.synchronize()
+        f_ms = e0.elapsed_time(e1) / 2
+        ctx.profile(True)
+        sysm.pulay_forces(D, Q, v, precision=prec, out=F)
+        fprof = ctx.profile_read()
+        ctx.profile(False)
+        grad["pulay_forces"] = {"ms": round(f_ms, 3), "vs_density": round(f_ms / float(np.mean(n_ms)), 3),
+                                "kernels_ms": {k: round(t, 3) for k, (c, t) in fprof.items()}}
+        log("local Pulay forces: %.2f ms (%.2fx the density alone); kernels: %s" % (
+            f_ms, f_ms / float(np.mean(n_ms)), grad["pulay_forces"]["kernels_ms"]))
+        del Q, F
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -81,6 +81,8 @@ struct DevSeg {
                              // interleaved; density-gradient launches only)
     double* gn;              // density gradient [n_points][3], caller order
     const double* wa;        // batch-ordered w*a, 3 per point (Hamiltonian with a vector field)
+    const double* Q;         // energy-weighted density matrix (forces), row-major, ld = n_basis
+    double* fb;              // per-function force accumulator [n_basis][3] (forces)
     int64_t ld;              // n_basis
     int64_t unit_begin, unit_count, unit_prefix;
     int64_t item_begin, item_count, item_prefix;
@@ -113,6 +115,13 @@ hipError_t launch_n_grad(Mode mode, const DevSeg* segs_dev, int n_segs, int64_t 
 // Hamiltonian with a vector field (FP64 or FP32 modes): H[I, J] += Phi_I^T L_J + L_I^T Phi_J over
 // 64-wide tile pairs I <= J, L from the basis launch with EXTRA_GGA_L.
 hipError_t launch_h_gga(Mode mode, const DevSeg* segs_dev, int n_segs, int64_t n_items, hipStream_t st);
+// Local Pulay forces (FP64 or FP32 modes), density items walked over the whole list twice:
+// fb[j] += sum_p grad phi_pj [(w v)_p (Phi D)_pj - w_p (Phi Q)_pj]; gphi from the basis launch
+// with EXTRA_GRAD, wv batch-ordered w*v.
+hipError_t launch_n_force(Mode mode, const DevSeg* segs_dev, int n_segs, int64_t n_items, hipStream_t st);
+// F[a] = 2 sum over the functions i of atom a (atom_first[a] <= i < atom_first[a + 1]) of fb[i].
+hipError_t launch_force_atoms(const double* fb, const int64_t* atom_first, int64_t n_atoms, double* F,
+                              hipStream_t st);
 hipError_t launch_wa(const double* pw, const int32_t* perm, const double* a_caller, double* wa, int64_t n_points,
                      hipStream_t st);
 hipError_t launch_fill(double* p, int64_t n, double value, hipStream_t st);

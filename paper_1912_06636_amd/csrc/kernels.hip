@@ -794,10 +794,20 @@ __global__ __launch_bounds__(512) void h_kernel_wide(const DevSeg* __restrict__ 
 // chunk is prefetched into registers while the MFMAs of the current one run.  NW waves: wave w
 // owns column block w % 4 and row blocks w / 4, w / 4 + NW / 4, ...  T = FP32 accumulates the
 // whole column tile in FP32; the row dot and the sum over tiles and units are FP64.
-template <typename T, int NW, int KC, bool DB, bool GRAD = false>
+//
+// KIND = NK_GRADIENT: T[:, J] = Phi D[:, J] over the whole list (coefficient 1, the lower
+// triangle read transposed) and four row dots, n and grad n = 2 T . grad Phi.
+// KIND = NK_FORCE: the list is walked twice, M[:, J] = diag(w v) Phi D[:, J] - diag(w) Phi Q[:, J]
+// (the row weights applied to Phi as it is staged), and the epilogue takes column sums,
+// f_j += sum_p grad phi_pj M_pj, into the per-function accumulator fb[N_b][3].
+enum NKind { NK_DENSITY = 0, NK_GRADIENT = 1, NK_FORCE = 2 };
+template <typename T, int NW, int KC, bool DB, int KIND = NK_DENSITY>
 __global__ __launch_bounds__(64 * NW) void n_kernel(const DevSeg* __restrict__ segs, int n_segs, int64_t total)
 {
     typedef Mma<T> M;
+    constexpr bool GRAD = KIND == NK_GRADIENT;
+    constexpr bool FORCE = KIND == NK_FORCE;
+    constexpr bool FULL = KIND != NK_DENSITY;  // contraction over the whole list
     constexpr int NT = 64 * NW;                              // threads
     constexpr int RB = 64 / NW;                              // row blocks per wave (16 row x 4 column blocks)
     constexpr int RS = NW / 4;                               // row-block stride between the waves of a column
@@ -806,6 +816,7 @@ __global__ __launch_bounds__(64 * NW) void n_kernel(const DevSeg* __restrict__ s
     constexpr int NB = DB ? 2 : 1;                           // LDS buffers
     static_assert(ND >= 1 && NA % 2 == 0 && RB % 4 == 0 && NT % TILE == 0 && TILE % KC == 0 && KC % 4 == 0,
                   "tile geometry");
+    static_assert(!FORCE || RS * TILE * 3 <= 4 * MAX_UNIT_POINTS, "force partials fit in red");
     __shared__ T As[NB][MAX_UNIT_POINTS][KC + 1];
     __shared__ T Bs[NB][KC][TILE + 2];
     constexpr int NQ = GRAD ? 4 : 1;                         // row dots: n, or n and the three gradient components
@@ -829,8 +840,11 @@ __global__ __launch_bounds__(64 * NW) void n_kernel(const DevSeg* __restrict__ s
         const int P = (np + 15) >> 4;
         const int J0 = it.tj * TILE;
         // chunk c covers columns KC c .. KC c + KC - 1: the tiles I <= J, or all tiles for the
-        // gradient (T = Phi D over the whole list)
-        const int n_chunks = (GRAD ? (m + TILE - 1) / TILE : it.tj + 1) * (TILE / KC);
+        // gradient (T = Phi D over the whole list); the forces walk the list once against D and
+        // once against Q (chunk c + half covers the columns of chunk c)
+        const int half = (FULL ? (m + TILE - 1) / TILE : it.tj + 1) * (TILE / KC);
+        const int n_chunks = FORCE ? 2 * half : half;
+        auto col0 = [&](int c) { return KC * (FORCE && c >= half ? c - half : c); };
         const int cjd = J0 + (tid & (TILE - 1));              // this thread's D column in every chunk
         const int64_t gjd = fn[min(cjd, m - 1)];
 
@@ -849,22 +863,35 @@ __global__ __launch_bounds__(64 * NW) void n_kernel(const DevSeg* __restrict__ s
             int32_t gcur[ND], gnxt[ND];
             auto load_idx = [&](int c, int32_t* g) {
 #pragma unroll
-                for (int q = 0; q < ND; ++q) g[q] = fn[min(KC * c + (tid >> 6) + (NT / TILE) * q, m - 1)];
+                for (int q = 0; q < ND; ++q) g[q] = fn[min(col0(c) + (tid >> 6) + (NT / TILE) * q, m - 1)];
             };
+            // forces: weights of this thread's staged rows, w v for the D pass and -w for the Q pass
+            double swv[FORCE ? NAR : 1], sw[FORCE ? NAR : 1];
+            if constexpr (FORCE) {
+                gp<const double> pw = gptr(sg.sys->pw + u.point_begin);
+                gp<const double> wv = gptr(sg.wv + u.point_begin);
+#pragma unroll
+                for (int q = 0; q < NAR; ++q) {
+                    const int row = min((tid + NT * q) / KC, np - 1);
+                    swv[q] = wv[row];
+                    sw[q] = -pw[row];
+                }
+            }
             auto fetch = [&](int c) {
 #pragma unroll
                 for (int q = 0; q < NAR; ++q) {
                     const int e = tid + NT * q;
-                    pa[q] = phi[(int64_t)min(e / KC, np - 1) * ld + KC * c + (e % KC)];
+                    pa[q] = phi[(int64_t)min(e / KC, np - 1) * ld + col0(c) + (e % KC)];
                 }
                 const bool diag = c / (TILE / KC) == it.tj;
+                gp<const double> src = FORCE && c >= half ? gptr(sg.Q) : D;
 #pragma unroll
                 for (int q = 0; q < ND; ++q) {
-                    const int ci = KC * c + (tid >> 6) + (NT / TILE) * q;
+                    const int ci = col0(c) + (tid >> 6) + (NT / TILE) * q;
                     // upper triangle only: the diagonal tile's lower part (every tile's, for the
-                    // gradient) is read transposed
-                    const bool lower = (GRAD || diag) && ci > cjd;
-                    pd[q] = D[lower ? gjd * ldd + gcur[q] : (int64_t)gcur[q] * ldd + gjd];
+                    // gradient and the forces) is read transposed
+                    const bool lower = (FULL || diag) && ci > cjd;
+                    pd[q] = src[lower ? gjd * ldd + gcur[q] : (int64_t)gcur[q] * ldd + gjd];
                 }
                 load_idx(c + 1, gnxt);
             };
@@ -875,13 +902,15 @@ __global__ __launch_bounds__(64 * NW) void n_kernel(const DevSeg* __restrict__ s
 #pragma unroll
                 for (int q = 0; q < NAR; ++q) {
                     const int e = tid + NT * q;
-                    As[buf][e / KC][e % KC] = (e / KC) < np ? pa[q] : T(0);
+                    T x = pa[q];
+                    if constexpr (FORCE) x = T((double)x * (c >= half ? sw[q] : swv[q]));
+                    As[buf][e / KC][e % KC] = (e / KC) < np ? x : T(0);
                 }
 #pragma unroll
                 for (int q = 0; q < ND; ++q) {
                     const int e = tid + NT * q;
-                    const bool ok = KC * c + (e >> 6) < m && cjd < m;
-                    Bs[buf][e >> 6][e & 63] = ok ? T((GRAD || diag) ? pd[q] : 2.0 * pd[q]) : T(0);
+                    const bool ok = col0(c) + (e >> 6) < m && cjd < m;
+                    Bs[buf][e >> 6][e & 63] = ok ? T((FULL || diag) ? pd[q] : 2.0 * pd[q]) : T(0);
                 }
             };
 
@@ -912,8 +941,36 @@ __global__ __launch_bounds__(64 * NW) void n_kernel(const DevSeg* __restrict__ s
             }
             mfma_chunk(DB ? ((n_chunks - 1) & 1) : 0);
 
-            // n_p += sum_j T[p][j] Phi[p][j]
             const int cj = J0 + cb * 16 + lr;
+            if constexpr (FORCE) {
+                // f_j += sum_p grad phi_pj M_pj: this wave's rows, then the lanes of one column
+                gp<const T> gph = gptr(static_cast<const T*>(sg.gphi) + 3 * u.out_offset);
+                double f[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+                for (int q = 0; q < R; ++q) {
+                    const int pblk = RS * q + rh;
+                    if (pblk < P) {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const int p = pblk * 16 + M::row(lk, r);
+                            const int64_t e = (int64_t)min(p, np - 1) * ld + cj;
+                            const double a = p < np && cj < m ? (double)acc[q][r] : 0.0;
+#pragma unroll
+                            for (int k = 0; k < 3; ++k) f[k] += a * (double)gph[3 * e + k];
+                        }
+                    }
+                }
+                double(*fred)[RS][TILE] = reinterpret_cast<double(*)[RS][TILE]>(&red[0][0][0]);
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    double v = f[k];
+                    v += __shfl_xor(v, 16);
+                    v += __shfl_xor(v, 32);
+                    if (lk == 0) fred[k][rh][cb * 16 + lr] = v;
+                }
+                return;
+            }
+            // n_p += sum_j T[p][j] Phi[p][j]
 #pragma unroll
             for (int q = 0; q < R; ++q) {
                 const int pblk = RS * q + rh;
@@ -952,7 +1009,18 @@ __global__ __launch_bounds__(64 * NW) void n_kernel(const DevSeg* __restrict__ s
             else run(Half{}, std::integral_constant<int, 0>{});
         }
         __syncthreads();
-        if (tid < np) {
+        if constexpr (FORCE) {
+            if (tid < 3 * TILE) {
+                const int k = tid / TILE, col = tid % TILE;
+                if (J0 + col < m) {
+                    double(*fred)[RS][TILE] = reinterpret_cast<double(*)[RS][TILE]>(&red[0][0][0]);
+                    double v = 0.0;
+#pragma unroll
+                    for (int h = 0; h < RS; ++h) v += fred[k][h][col];
+                    gadd(gptr(sg.fb) + 3 * (int64_t)fn[J0 + col] + k, v);
+                }
+            }
+        } else if (tid < np) {
             const int32_t pc = gptr(sg.sys->perm)[u.point_begin + tid];
             const double v = (red[0][0][tid] + red[0][1][tid]) + (red[0][2][tid] + red[0][3][tid]);
             gadd(gptr(sg.n) + pc, v);
@@ -1353,8 +1421,21 @@ hipError_t launch_n_grad(Mode mode, const DevSeg* segs_dev, int n_segs, int64_t 
     if (n_items > 0x7ffffff0) return hipErrorInvalidValue;
     const dim3 g(grid_for(n_items, 0)), b(1024);
     switch (mode) {
-    case MODE_FP64: hipLaunchKernelGGL((n_kernel<double, 16, 16, true, true>), g, b, 0, st, segs_dev, n_segs, n_items); break;
-    case MODE_FP32: hipLaunchKernelGGL((n_kernel<float, 16, 16, true, true>), g, b, 0, st, segs_dev, n_segs, n_items); break;
+    case MODE_FP64: hipLaunchKernelGGL((n_kernel<double, 16, 16, true, NK_GRADIENT>), g, b, 0, st, segs_dev, n_segs, n_items); break;
+    case MODE_FP32: hipLaunchKernelGGL((n_kernel<float, 16, 16, true, NK_GRADIENT>), g, b, 0, st, segs_dev, n_segs, n_items); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_n_force(Mode mode, const DevSeg* segs_dev, int n_segs, int64_t n_items, hipStream_t st)
+{
+    if (n_items <= 0 || n_segs <= 0) return hipSuccess;
+    if (n_items > 0x7ffffff0) return hipErrorInvalidValue;
+    const dim3 g(grid_for(n_items, 0)), b(1024);
+    switch (mode) {
+    case MODE_FP64: hipLaunchKernelGGL((n_kernel<double, 16, 16, true, NK_FORCE>), g, b, 0, st, segs_dev, n_segs, n_items); break;
+    case MODE_FP32: hipLaunchKernelGGL((n_kernel<float, 16, 16, true, NK_FORCE>), g, b, 0, st, segs_dev, n_segs, n_items); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1380,6 +1461,27 @@ __global__ void fill_kernel(double* __restrict__ p, int64_t n, double value)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = value;
+}
+
+__global__ void force_atoms_kernel(const double* __restrict__ fb, const int64_t* __restrict__ atom_first,
+                                   int64_t n_atoms, double* __restrict__ F)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 3 * n_atoms) return;
+    const int64_t a = i / 3, k = i - 3 * a;
+    double v = 0.0;
+    for (int64_t j = atom_first[a]; j < atom_first[a + 1]; ++j) v += fb[3 * j + k];
+    F[i] = 2.0 * v;
+}
+
+hipError_t launch_force_atoms(const double* fb, const int64_t* atom_first, int64_t n_atoms, double* F,
+                              hipStream_t st)
+{
+    if (n_atoms <= 0) return hipSuccess;
+    const int64_t blocks = (3 * n_atoms + 255) / 256;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(force_atoms_kernel, dim3((unsigned)blocks), dim3(256), 0, st, fb, atom_first, n_atoms, F);
+    return hipGetLastError();
 }
 
 hipError_t launch_fill(double* p, int64_t n, double value, hipStream_t st)
@@ -1408,7 +1510,6 @@ hipError_t launch_wv(const double* pw, const int32_t* perm, const double* v_call
     return hipGetLastError();
 }
 
-// H[j][i] = H[i][j] for i < j, through 32x32 LDS tiles (coalesced on both sides).
 __global__ void wa_kernel(const double* __restrict__ pw, const int32_t* __restrict__ perm,
                           const double* __restrict__ a, double* __restrict__ wa, int64_t n)
 {
@@ -1427,6 +1528,7 @@ hipError_t launch_wa(const double* pw, const int32_t* perm, const double* a_call
     return hipGetLastError();
 }
 
+// H[j][i] = H[i][j] for i < j, through 32x32 LDS tiles (coalesced on both sides).
 __global__ __launch_bounds__(256) void mirror_kernel(double* __restrict__ H, int64_t n)
 {
     __shared__ double t[32][33];

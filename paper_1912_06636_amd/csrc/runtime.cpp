@@ -281,7 +281,7 @@ struct nao_system_s {
     DevArray d_sys, d_px, d_py, d_pz, d_pw, d_perm, d_atoms, d_species, d_shell_ptr, d_shell_l, d_shell_rad,
         d_radial_par, d_spline, d_fn_ptr, d_fn_code;
     DevArray d_units, d_unit_atoms, d_unit_cols, d_unit_fn, d_h_items, d_hw_items, d_n_items;
-    DevArray d_wv, d_v, d_D, d_H, d_n, d_gn, d_a, d_wa, d_segs;
+    DevArray d_wv, d_v, d_D, d_H, d_n, d_gn, d_a, d_wa, d_segs, d_Q, d_fb, d_atom_first, d_F;
     int spline_lds = 0;  // doubles of spline table staged in LDS by the basis kernel (0 = not staged)
 };
 
@@ -293,7 +293,8 @@ size_t system_bytes(const nao_system_s* s)
                              &s->d_species, &s->d_shell_ptr, &s->d_shell_l, &s->d_shell_rad, &s->d_radial_par,
                              &s->d_spline, &s->d_fn_ptr, &s->d_fn_code, &s->d_units, &s->d_unit_atoms, &s->d_unit_cols, &s->d_unit_fn,
                              &s->d_h_items, &s->d_hw_items, &s->d_n_items, &s->d_wv, &s->d_v, &s->d_D, &s->d_H, &s->d_n,
-                             &s->d_gn, &s->d_a, &s->d_wa, &s->d_segs};
+                             &s->d_gn, &s->d_a, &s->d_wa, &s->d_segs, &s->d_Q, &s->d_fb, &s->d_atom_first,
+                             &s->d_F};
     size_t t = 0;
     for (auto* a : arr) t += a->bytes;
     return t;
@@ -304,7 +305,8 @@ void free_all(nao_system_s* s)
     DevArray* arr[] = {&s->d_sys, &s->d_px, &s->d_py, &s->d_pz, &s->d_pw, &s->d_perm, &s->d_atoms,
                        &s->d_species, &s->d_shell_ptr, &s->d_shell_l, &s->d_shell_rad, &s->d_radial_par,
                        &s->d_spline, &s->d_fn_ptr, &s->d_fn_code, &s->d_units, &s->d_unit_atoms, &s->d_unit_cols, &s->d_unit_fn,
-                       &s->d_h_items, &s->d_hw_items, &s->d_n_items, &s->d_wv, &s->d_v, &s->d_D, &s->d_H, &s->d_n, &s->d_gn, &s->d_a, &s->d_wa, &s->d_segs};
+                       &s->d_h_items, &s->d_hw_items, &s->d_n_items, &s->d_wv, &s->d_v, &s->d_D, &s->d_H, &s->d_n, &s->d_gn, &s->d_a, &s->d_wa, &s->d_segs,
+                       &s->d_Q, &s->d_fb, &s->d_atom_first, &s->d_F};
     for (auto* a : arr) {
         dev_free(s->ctx, a->p, a->bytes);
         a->p = nullptr;
@@ -1544,6 +1546,78 @@ nao_status nao_update_density_gradient(nao_system s, const double* D, nao_memspa
         HIP_TRY(c, hipMemcpyAsync(gout, gd, 3 * n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     }
     if (out_space == NAO_MEM_HOST || D_space == NAO_MEM_HOST) HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return NAO_OK;
+}
+
+nao_status nao_pulay_forces(nao_system s, const double* D, const double* Q, const double* v, nao_memspace in_space,
+                            nao_precision prec, double* F, nao_memspace F_space)
+{
+    if (!s) return (g_thread_error = "system is NULL", NAO_ERR_INVALID_ARG);
+    nao_ctx c = s->ctx;
+    nao_status st = check_ctx(c);
+    if (st != NAO_OK) return st;
+    if (prec != NAO_FP64 && prec != NAO_FP32)
+        return (set_err(c, "the forces run in FP64 or FP32"), NAO_ERR_INVALID_ARG);
+    const int64_t n = s->n_points, nb = s->basis.n_basis, na = s->basis.n_atoms;
+    if (!F || (nb > 0 && (!D || !Q)) || (n > 0 && !v)) return (set_err(c, "NULL D, Q, v or F"), NAO_ERR_INVALID_ARG);
+    if ((in_space != NAO_MEM_HOST && in_space != NAO_MEM_DEVICE) || (F_space != NAO_MEM_HOST && F_space != NAO_MEM_DEVICE))
+        return (set_err(c, "bad memspace"), NAO_ERR_INVALID_ARG);
+    if ((st = ensure_gscratch(s, 3)) != NAO_OK) return st;  // gradients: 3 per basis value
+    const double* Dd = D;
+    const double* Qd = Q;
+    const double* vd = v;
+    if (in_space == NAO_MEM_HOST) {
+        if (nb > 0) {
+            if ((st = ensure(c, s->d_D, nb * nb * sizeof(double))) != NAO_OK) return st;
+            if ((st = ensure(c, s->d_Q, nb * nb * sizeof(double))) != NAO_OK) return st;
+            HIP_TRY(c, hipMemcpyAsync(s->d_D.p, D, nb * nb * sizeof(double), hipMemcpyHostToDevice, c->stream));
+            HIP_TRY(c, hipMemcpyAsync(s->d_Q.p, Q, nb * nb * sizeof(double), hipMemcpyHostToDevice, c->stream));
+            Dd = s->d_D.as<double>();
+            Qd = s->d_Q.as<double>();
+        }
+        if (n > 0) {
+            if ((st = ensure(c, s->d_v, n * sizeof(double))) != NAO_OK) return st;
+            HIP_TRY(c, hipMemcpyAsync(s->d_v.p, v, n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+            vd = s->d_v.as<double>();
+        }
+    }
+    if ((st = ensure(c, s->d_fb, std::max<int64_t>(1, 3 * nb) * sizeof(double))) != NAO_OK) return st;
+    if ((st = ensure(c, s->d_atom_first, (na + 1) * sizeof(int64_t))) != NAO_OK) return st;
+    HIP_TRY(c, hipMemcpyAsync(s->d_atom_first.p, s->basis.atom_first.data(), (na + 1) * sizeof(int64_t),
+                              hipMemcpyHostToDevice, c->stream));
+    double* Fd = F;
+    if (F_space == NAO_MEM_HOST) {
+        if ((st = ensure(c, s->d_F, std::max<int64_t>(1, 3 * na) * sizeof(double))) != NAO_OK) return st;
+        Fd = s->d_F.as<double>();
+    }
+    LAUNCH(c, "fill", launch_fill(s->d_fb.as<double>(), 3 * nb, 0.0, c->stream));
+    LAUNCH(c, "wv", launch_wv(s->d_pw.as<double>(), s->d_perm.as<int32_t>(), vd, s->d_wv.as<double>(), n, c->stream));
+    const Mode mode = exec_mode(c, prec);
+    const bool f32 = prec != NAO_FP64;
+    std::vector<DevSeg> segs;
+    for (const Block& b : s->blocks) {
+        DevSeg g = make_seg(s, b, false);
+        g.D = Dd;
+        g.Q = Qd;
+        g.wv = s->d_wv.as<double>();
+        g.fb = s->d_fb.as<double>();
+        g.gphi = c->gscratch;
+        segs.push_back(g);
+    }
+    if (!segs.empty()) {
+        HIP_TRY(c, hipMemcpyAsync(s->d_segs.p, segs.data(), segs.size() * sizeof(DevSeg), hipMemcpyHostToDevice,
+                                  c->stream));
+        DevSeg* dseg = s->d_segs.as<DevSeg>();
+        for (size_t k = 0; k < segs.size(); ++k) {
+            LAUNCH(c, f32 ? "basis_grad_f32" : "basis_grad_f64",
+                   launch_basis(dseg + k, 1, segs[k].unit_count, s->spline_lds, f32, c->stream, 0, EXTRA_GRAD));
+            LAUNCH(c, f32 ? "nforce_f32" : "nforce_f64", launch_n_force(mode, dseg + k, 1, segs[k].item_count, c->stream));
+        }
+    }
+    LAUNCH(c, "force_atoms", launch_force_atoms(s->d_fb.as<double>(), s->d_atom_first.as<int64_t>(), na, Fd, c->stream));
+    if (F_space == NAO_MEM_HOST && na > 0)
+        HIP_TRY(c, hipMemcpyAsync(F, Fd, 3 * na * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    if (F_space == NAO_MEM_HOST || in_space == NAO_MEM_HOST) HIP_TRY(c, hipStreamSynchronize(c->stream));
     return NAO_OK;
 }
 

@@ -84,6 +84,7 @@ _sig("nao_eval_basis", _S, _vp, ctypes.c_int64, ctypes.c_int64, _vp, ctypes.c_in
 _sig("nao_integrate_h", _S, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int)
 _sig("nao_update_density", _S, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int, _c_dp)
 _sig("nao_update_density_gradient", _S, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_int)
+_sig("nao_pulay_forces", _S, _vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int)
 _sig("nao_integrate_h_gga", _S, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int)
 _sig("nao_system_destroy", None, _vp)
 _sig("nao_run_many", _S, _vp, ctypes.POINTER(Work), ctypes.c_int64, ctypes.c_int, ctypes.c_uint32)
@@ -104,6 +105,7 @@ EXPORTED = [
     "nao_ctx_synchronize", "nao_ctx_memory", "nao_ctx_profile", "nao_ctx_profile_read", "nao_plan_create", "nao_plan_info", "nao_plan_get_batches",
     "nao_plan_destroy", "nao_build_batches", "nao_system_set_group_max", "nao_system_set_h_tile", "nao_system_autotune", "nao_system_info", "nao_get_batches",
     "nao_system_work", "nao_eval_basis", "nao_integrate_h", "nao_update_density", "nao_update_density_gradient", "nao_integrate_h_gga",
+    "nao_pulay_forces",
     "nao_system_destroy",
     "nao_run_many", "nao_server_create", "nao_server_open_session", "nao_server_close_session",
     "nao_server_session_info", "nao_server_submit", "nao_server_step", "nao_server_poll", "nao_server_result",
@@ -285,6 +287,7 @@ class System:
         self.handle = h
         ctx._children.add(self)
         self.n_points = len(xyz)
+        self.n_atoms = int(d.struct.n_atoms)
         info = self.info()
         self.n_basis, self.n_batches, self.n_list = info[0], info[1], info[2]
 
@@ -397,6 +400,19 @@ class System:
         _check(_lib.nao_update_density_gradient(self.handle, pd, sd, PRECISIONS[precision], pn, pg, sn),
                self.ctx.handle)
         return out, out_grad
+
+    def pulay_forces(self, D, Q, v, precision="fp64", out=None):
+        """nao_pulay_forces: local Pulay forces [n_atoms, 3]; D, Q and v share a memory space."""
+        pd, sd, kd = _ptr_space(D)
+        pq, sq, kq = _ptr_space(Q)
+        pv, sv, kv = _ptr_space(v)
+        if not (sd == sq == sv):
+            raise ValueError("D, Q and v must be in the same memory space")
+        if out is None:
+            out = np.empty((self.n_atoms, 3), np.float64)
+        pf, sf, kf = _ptr_space(out)
+        _check(_lib.nao_pulay_forces(self.handle, pd, pq, pv, sd, PRECISIONS[precision], pf, sf), self.ctx.handle)
+        return out
 
 
 # ---------------------------------------------------------------------------------------------

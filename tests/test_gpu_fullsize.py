@@ -164,3 +164,27 @@ def test_fp64_gga_hamiltonian_sampled_against_oracle(nao, cfg):
     e = float(np.max(np.abs(got - ref))) / float(np.max(np.abs(H)))
     say("config", cfg, "sampled e_H %.3e over %d pairs" % (e, len(pairs)))
     assert e <= 1e-12
+
+
+@pytest.mark.parametrize("cfg", [2, 4])
+def test_fp64_forces_sampled_against_oracle(nao, cfg):
+    say("full-size local Pulay forces vs oracle samples, config", cfg)
+    from workloads import generate as g
+    w, B = full(cfg)
+    Q = g.energy_weighted_for(w, 1)
+    ctx = nao.Context(0)
+    s = nao.build_batches(ctx, w["basis"], w["xyz"], w["w"], w["max_batch"])
+    F = s.pulay_forces(w["D"], Q, w["v"])
+    _, gD = s.update_density_gradient(w["D"])
+    _, gQ = s.update_density_gradient(Q)
+    s.close()
+    ctx.close()
+    scale = float(np.max(np.abs(F)))
+    # every atom at once: sum_A F_A = sum_p w_p [v_p grad n_D - grad n_Q]
+    tot = ((w["w"] * w["v"])[:, None] * gD - w["w"][:, None] * gQ).sum(axis=0)
+    assert float(np.max(np.abs(F.sum(axis=0) - tot))) <= 1e-12 * scale
+    atoms = [int(np.argmax(np.abs(F).max(axis=1)))] + ([len(F) // 3] if cfg == 2 else [])
+    ref = oi.pulay_forces_at(B, w["xyz"], w["w"], w["v"], w["D"], Q, atoms)
+    e = float(np.max(np.abs(F[atoms] - ref))) / scale
+    say("config", cfg, "sampled e_F %.3e over atoms %s" % (e, atoms))
+    assert e <= 1e-12

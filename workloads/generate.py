@@ -28,7 +28,7 @@ import threading
 
 import numpy as np
 
-STREAM_GEOMETRY, STREAM_RADIAL, STREAM_POTENTIAL, STREAM_DENSITY, STREAM_ARRIVAL = range(5)
+STREAM_GEOMETRY, STREAM_RADIAL, STREAM_POTENTIAL, STREAM_DENSITY, STREAM_ARRIVAL, STREAM_ENERGY = range(6)
 
 N_KNOTS = 200
 R_MIN = 1.0e-4
@@ -343,6 +343,28 @@ def density_matrix(basis, n_occ, d_max, rng):
         far = dd > d_max
         D[far[ba][:, ba]] = 0.0
     return np.ascontiguousarray(D), C
+
+
+def energy_weighted_matrix(basis, C, d_max, rng):
+    """Q = C diag(e) C^T with seeded level energies e ~ U(-1, -0.05) (occupied levels lie below
+    zero), the same coefficients C as D and the same distance cut.  Exactly symmetric."""
+    e = np.sort(rng.uniform(-1.0, -0.05, size=C.shape[1]))
+    Q = (C * e[None, :]) @ C.T
+    Q = 0.5 * (Q + Q.T)
+    if d_max is not None:
+        ba = basis_atom_index(basis)
+        xyz = basis["atom_xyz"]
+        dd = np.sqrt(((xyz[:, None, :] - xyz[None, :, :]) ** 2).sum(axis=2))
+        Q[(dd > d_max)[ba][:, ba]] = 0.0
+    return np.ascontiguousarray(Q)
+
+
+def energy_weighted_for(w, seed: int = 0):
+    """Q for a workload that carries its coefficients C (its configuration's distance cut and
+    random stream; workloads without a configuration use no cut)."""
+    cfg, st = int(w.get("cfg", 0)), int(w.get("structure", 0))
+    d_max = CONFIGS[cfg]["d_max"] if cfg in CONFIGS else None
+    return energy_weighted_matrix(w["basis"], w["C"], d_max, rng_for(cfg, st, STREAM_ENERGY, seed))
 
 
 # ----------------------------------------------------------------------------------------------
