@@ -16,6 +16,11 @@ the components of u), grad phi = R'(r) u Y + (R/r) (G - u (u . G)), the chain
 rule through du/dr = (I - u u^T)/r.  Reading: grad phi = 0 where phi is zero by
 the cutoff test and for |r - R_A| <= rmin (the clamped, constant part of the
 spline).
+
+Laplacian (for the kinetic term -1/2 lap of the Hamiltonian): Y_lm is a spherical
+harmonic of degree l, so lap phi = (R'' + 2 R'/r - l(l+1) R/r^2) Y_lm(u), with the
+radial factor from the spline (oracle.spline.radial_laplacian); zero where grad phi
+is zero by the reading above.
 """
 from __future__ import annotations
 
@@ -115,6 +120,35 @@ class Basis:
             g = dR[:, None] * u * Y[:, lm][:, None] + (R / safe)[:, None] * Gt[:, lm, :]
             out[:, c, :] = np.where(ok[:, None], g, 0.0)
         return out
+
+    def lap_phi_atom(self, pts, a) -> np.ndarray:
+        """Laplacian of every basis function of atom a at pts[n, 3] -> [n, nfn(a)]."""
+        pts = np.asarray(pts, dtype=np.float64).reshape(-1, 3)
+        X = self.atom_xyz[a]
+        dx = pts[:, 0] - X[0]
+        dy = pts[:, 1] - X[1]
+        dz = pts[:, 2] - X[2]
+        d2 = (dx * dx + dy * dy) + dz * dz
+        r = np.sqrt(d2)
+        safe = np.where(r > 0.0, r, 1.0)
+        u = np.stack([np.where(r > 0.0, dx / safe, 0.0), np.where(r > 0.0, dy / safe, 0.0),
+                      np.where(r > 0.0, dz / safe, 1.0)], axis=1)
+        Y = real_ylm(u)
+        fns = range(self.atom_first[a], self.atom_first[a + 1])
+        out = np.zeros((len(pts), len(fns)))
+        for c, i in enumerate(fns):
+            sp = self.splines[self.fn_radial[i]]
+            ok = (d2 < sp.rcut * sp.rcut) & (r > sp.rmin)
+            lap = sp.laplacian_at_r(r, int(self.fn_l[i]))
+            out[:, c] = np.where(ok, lap * Y[:, self.fn_lm[i]], 0.0)
+        return out
+
+    def lap_phi(self, pts, atoms) -> np.ndarray:
+        """Laplacian of the functions of `atoms` (ascending) at pts -> [n, m]."""
+        pts = np.asarray(pts, dtype=np.float64).reshape(-1, 3)
+        if len(atoms) == 0:
+            return np.zeros((len(pts), 0))
+        return np.concatenate([self.lap_phi_atom(pts, a) for a in atoms], axis=1)
 
     def grad_phi(self, pts, atoms) -> np.ndarray:
         """grad phi of the functions of `atoms` (ascending) at pts -> [n, m, 3]."""

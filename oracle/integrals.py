@@ -121,6 +121,71 @@ def hamiltonian_gga_entries(basis, xyz, w, v, a, pairs) -> np.ndarray:
     return out
 
 
+def hamiltonian_ks(basis, xyz, w, v, a=None, chunks=None) -> np.ndarray:
+    """h_ij = sum_p w_p [phi_i (t + v) phi_j + a_p . grad(phi_i phi_j)] at r_p, t = -1/2 lap the
+    (non-relativistic) kinetic operator, symmetrised in i and j: eq. H_int_aims with h_KS
+    acting on phi_j as t + v, plus the vector-field term of hamiltonian_gga (a None: none).
+    Batch form of eq. batch_matrix_mult, h = K^T L + L^T K with K = Phi and
+    L = (w v / 2) Phi - (w / 4) lap Phi + sum_k (w a_k) dPhi/dx_k."""
+    xyz = np.asarray(xyz, dtype=np.float64).reshape(-1, 3)
+    w = np.asarray(w, dtype=np.float64)
+    wv = w * np.asarray(v, dtype=np.float64)
+    wa = None if a is None else w[:, None] * np.asarray(a, dtype=np.float64).reshape(-1, 3)
+    H = np.zeros((basis.n_basis, basis.n_basis))
+    for idx in (chunks if chunks is not None else cell_chunks(xyz)):
+        atoms = relevant_atoms_of_points(xyz[idx], basis.atom_xyz, basis.atom_rcut)
+        if len(atoms) == 0:
+            continue
+        fns = basis.functions_of(atoms)
+        Phi = basis.phi(xyz[idx], atoms)
+        L = 0.5 * wv[idx][:, None] * Phi - 0.25 * w[idx][:, None] * basis.lap_phi(xyz[idx], atoms)
+        if wa is not None:
+            G = basis.grad_phi(xyz[idx], atoms)
+            for k in range(3):
+                L = L + wa[idx, k][:, None] * G[:, :, k]
+        H[np.ix_(fns, fns)] += Phi.T @ L + L.T @ Phi
+    return 0.5 * (H + H.T)
+
+
+def kinetic(basis, xyz, w, chunks=None) -> np.ndarray:
+    """t_ij = sum_p w_p (phi_i t phi_j + phi_j t phi_i) / 2: hamiltonian_ks with v = 0, no field."""
+    return hamiltonian_ks(basis, xyz, w, np.zeros(len(w)), None, chunks)
+
+
+def hamiltonian_ks_entries(basis, xyz, w, v, a, pairs) -> np.ndarray:
+    """hamiltonian_ks's h_ij for selected (i, j) pairs (a may be None): sum over the points
+    inside both cutoff spheres (sampled checks at full size)."""
+    xyz = np.asarray(xyz, dtype=np.float64).reshape(-1, 3)
+    w = np.asarray(w, dtype=np.float64)
+    wv = w * np.asarray(v, dtype=np.float64)
+    wa = None if a is None else w[:, None] * np.asarray(a, dtype=np.float64).reshape(-1, 3)
+    out = np.zeros(len(pairs))
+    for k, (i, j) in enumerate(pairs):
+        fa, fb = int(basis.fn_atom[i]), int(basis.fn_atom[j])
+        sel = np.ones(len(xyz), dtype=bool)
+        for at in (fa, fb):
+            X = basis.atom_xyz[at]
+            dx = xyz[:, 0] - X[0]
+            dy = xyz[:, 1] - X[1]
+            dz = xyz[:, 2] - X[2]
+            sel &= ((dx * dx + dy * dy) + dz * dz) < basis.atom_rcut[at] * basis.atom_rcut[at]
+        idx = np.nonzero(sel)[0]
+        if len(idx) == 0:
+            continue
+        ia, jb = i - basis.atom_first[fa], j - basis.atom_first[fb]
+        pa = basis.phi_atom(xyz[idx], fa)[:, ia]
+        pb = basis.phi_atom(xyz[idx], fb)[:, jb]
+        la = basis.lap_phi_atom(xyz[idx], fa)[:, ia]
+        lb = basis.lap_phi_atom(xyz[idx], fb)[:, jb]
+        val = np.sum(wv[idx] * pa * pb) - 0.25 * np.sum(w[idx] * (pa * lb + la * pb))
+        if wa is not None:
+            ga = basis.grad_phi_atom(xyz[idx], fa)[:, ia, :]
+            gb = basis.grad_phi_atom(xyz[idx], fb)[:, jb, :]
+            val += np.sum(wa[idx] * (ga * pb[:, None] + pa[:, None] * gb))
+        out[k] = float(val)
+    return out
+
+
 def overlap(basis, xyz, w, chunks=None) -> np.ndarray:
     """s_ij on the grid: the v = 1 case of the Hamiltonian quadrature."""
     return hamiltonian(basis, xyz, w, np.ones(len(w)), chunks)

@@ -18,6 +18,13 @@ rmin < r < rcut, with dR/dt the derivative of the evaluation formula in u; the
 spline is constant in the clamped region r <= rmin, so dR/dr = 0 there, and
 dR/dr = 0 at and beyond the cutoff.
 
+Radial part of the Laplacian (for the kinetic term): for phi = R(r) Y_lm(unit r),
+lap phi = (R'' + 2 R'/r - l(l+1) R/r^2) Y_lm; with R' = S'/(Delta r) and
+R'' = (S'' - Delta S')/(Delta r)^2 in the spline variable this is
+(S''/Delta^2 + S'/Delta - l(l+1) S) / r^2, where S'' = (1-u) M_k + u M_{k+1} is the
+spline's own (piecewise linear) second derivative.  Reading: zero for r <= rmin
+and r >= rcut, like the derivative.
+
 Plain Python loops for the tridiagonal solve (Thomas algorithm).
 """
 from __future__ import annotations
@@ -78,6 +85,30 @@ def derivative_t(t, y, M) -> np.ndarray:
     return (y[k + 1] - y[k]) + ((1.0 - 3.0 * a * a) * M[k] + (3.0 * u * u - 1.0) * M[k + 1]) / 6.0
 
 
+def second_t(t, y, M) -> np.ndarray:
+    """d^2R/dt^2 of the cubic spline at (already clamped) coordinate t."""
+    t = np.asarray(t, dtype=np.float64)
+    n = len(y)
+    k = np.minimum(np.floor(t).astype(np.int64), n - 2)
+    u = t - k
+    return (1.0 - u) * M[k] + u * M[k + 1]
+
+
+def radial_laplacian(r, y, M, rmin: float, rcut: float, l: int) -> np.ndarray:
+    """R'' + 2 R'/r - l(l+1) R/r^2: zero for r <= rmin and for r >= rcut."""
+    r = np.asarray(r, dtype=np.float64)
+    n = len(y)
+    delta = math.log(rcut / rmin) / (n - 1)
+    inside = (r > rmin) & (r < rcut)
+    safe = np.where(inside, r, 1.0)
+    t = spline_t(safe, rmin, rcut, n)
+    S = evaluate_t(t, y, M)
+    dS = derivative_t(t, y, M)
+    d2S = second_t(t, y, M)
+    val = (d2S / (delta * delta) + dS / delta - l * (l + 1) * S) / (safe * safe)
+    return np.where(inside, val, 0.0)
+
+
 def radial_derivative(r, y, M, rmin: float, rcut: float) -> np.ndarray:
     """dR/dr: zero for r <= rmin (clamped, constant) and for r >= rcut."""
     r = np.asarray(r, dtype=np.float64)
@@ -108,3 +139,7 @@ class RadialSpline:
     def deriv_at_r(self, r) -> np.ndarray:
         """dR/dr (zero for r <= rmin and r >= rcut)."""
         return radial_derivative(r, self.y, self.M, self.rmin, self.rcut)
+
+    def laplacian_at_r(self, r, l: int) -> np.ndarray:
+        """R'' + 2 R'/r - l(l+1) R/r^2 (zero for r <= rmin and r >= rcut)."""
+        return radial_laplacian(r, self.y, self.M, self.rmin, self.rcut, l)
