@@ -205,8 +205,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip timing the plain FP64 per-batch path")
     ap.add_argument("--gradient", action="store_true",
-                    help="also time the gradient operations: the density with its gradient, the Hamiltonian "
-                         "with a vector field and the local Pulay forces")
+                    help="also time the extended operations: the density with its gradient, the Hamiltonian "
+                         "with a vector field and with the kinetic term, and the local Pulay forces")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="MiB copied once by a plain device copy (reference for counter scaling)")
@@ -341,70 +341,52 @@ def main():
 
     grad = None
     if args.gradient and prec in ("fp64", "fp32"):
-        # density and its gradient (same inputs and grouping as the timed step)
+        # the extended operations on the same inputs and grouping as the timed step
         sysm.set_group_max(group_max_used)
-        gn = torch.empty((sysm.n_points, 3), dtype=torch.float64, device=dev)
-        sysm.update_density_gradient(D, precision=prec, out=n, out_grad=gn)
-        torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        with torch.cuda.stream(stream):
-            e0.record(stream)
-            for _ in range(2):
-                sysm.update_density_gradient(D, precision=prec, out=n, out_grad=gn)
-            e1.record(stream)
-        torch.cuda.synchronize()
-        g_ms = e0.elapsed_time(e1) / 2
-        ctx.profile(True)
-        sysm.update_density_gradient(D, precision=prec, out=n, out_grad=gn)
-        gprof = ctx.profile_read()
-        ctx.profile(False)
-        grad = {"ms": round(g_ms, 3), "vs_density": round(g_ms / float(np.mean(n_ms)), 3),
-                "gpt_basis2_per_s": round(U / (g_ms * 1e-3) / 1e9, 3),
-                "kernels_ms": {k: round(t, 3) for k, (c, t) in gprof.items()}}
-        log("density + gradient: %.2f ms (%.2fx the density alone); kernels: %s" % (
-            g_ms, g_ms / float(np.mean(n_ms)), grad["kernels_ms"]))
+
+        def time_op(op):
+            """Mean of two calls on the library's stream, then one profiled call (ms per kernel)."""
+            op()
+            torch.cuda.synchronize()
+            with torch.cuda.stream(stream):
+                e0.record(stream)
+                for _ in range(2):
+                    op()
+                e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / 2
+            ctx.profile(True)
+            op()
+            prof = ctx.profile_read()
+            ctx.profile(False)
+            return ms, {k: round(t, 3) for k, (c, t) in prof.items()}
+
+        n_mean, h_mean = float(np.mean(n_ms)), float(np.mean(h_ms))
+        gn = torch.empty((sysm.n_points, 3), dtype=torch.float64, device=dev)
+        g_ms, kern = time_op(lambda: sysm.update_density_gradient(D, precision=prec, out=n, out_grad=gn))
+        grad = {"ms": round(g_ms, 3), "vs_density": round(g_ms / n_mean, 3),
+                "gpt_basis2_per_s": round(U / (g_ms * 1e-3) / 1e9, 3), "kernels_ms": kern}
+        log("density + gradient: %.2f ms (%.2fx the density alone); kernels: %s" % (g_ms, g_ms / n_mean, kern))
         del gn
-        # Hamiltonian with a seeded vector field (the GGA term)
+        # Hamiltonian with a seeded vector field (the GGA term), and with the kinetic term
         a = torch.from_numpy(0.3 * np.random.default_rng(99).normal(size=(sysm.n_points, 3))).to(dev)
-        sysm.integrate_h_gga(v, a, precision=prec, out=H)
-        torch.cuda.synchronize()
-        with torch.cuda.stream(stream):
-            e0.record(stream)
-            for _ in range(2):
-                sysm.integrate_h_gga(v, a, precision=prec, out=H)
-            e1.record(stream)
-        torch.cuda.synchronize()
-        gg_ms = e0.elapsed_time(e1) / 2
-        ctx.profile(True)
-        sysm.integrate_h_gga(v, a, precision=prec, out=H)
-        ggprof = ctx.profile_read()
-        ctx.profile(False)
-        grad["hamiltonian_with_field"] = {"ms": round(gg_ms, 3), "vs_hamiltonian": round(gg_ms / float(np.mean(h_ms)), 3),
-                                          "kernels_ms": {k: round(t, 3) for k, (c, t) in ggprof.items()}}
-        log("hamiltonian with a vector field: %.2f ms (%.2fx the local one); kernels: %s" % (
-            gg_ms, gg_ms / float(np.mean(h_ms)), grad["hamiltonian_with_field"]["kernels_ms"]))
+        ms, kern = time_op(lambda: sysm.integrate_h_gga(v, a, precision=prec, out=H))
+        grad["hamiltonian_with_field"] = {"ms": round(ms, 3), "vs_hamiltonian": round(ms / h_mean, 3),
+                                          "kernels_ms": kern}
+        log("hamiltonian with a vector field: %.2f ms (%.2fx the local one); kernels: %s" % (ms, ms / h_mean, kern))
+        ms, kern = time_op(lambda: sysm.integrate_h_ks(v, precision=prec, out=H))
+        grad["hamiltonian_kinetic"] = {"ms": round(ms, 3), "vs_hamiltonian": round(ms / h_mean, 3),
+                                       "kernels_ms": kern}
+        log("hamiltonian with the kinetic term: %.2f ms (%.2fx the local one); kernels: %s" % (ms, ms / h_mean, kern))
         del a
         # local Pulay forces with a seeded energy-weighted density matrix
         from workloads.generate import energy_weighted_for
         Q = torch.from_numpy(energy_weighted_for(work, 1)).to(dev)
         F = torch.empty((sysm.n_atoms, 3), dtype=torch.float64, device=dev)
-        sysm.pulay_forces(D, Q, v, precision=prec, out=F)
-        torch.cuda.synchronize()
-        with torch.cuda.stream(stream):
-            e0.record(stream)
-            for _ in range(2):
-                sysm.pulay_forces(D, Q, v, precision=prec, out=F)
-            e1.record(stream)
-        torch.cuda.synchronize()
-        f_ms = e0.elapsed_time(e1) / 2
-        ctx.profile(True)
-        sysm.pulay_forces(D, Q, v, precision=prec, out=F)
-        fprof = ctx.profile_read()
-        ctx.profile(False)
-        grad["pulay_forces"] = {"ms": round(f_ms, 3), "vs_density": round(f_ms / float(np.mean(n_ms)), 3),
-                                "kernels_ms": {k: round(t, 3) for k, (c, t) in fprof.items()}}
-        log("local Pulay forces: %.2f ms (%.2fx the density alone); kernels: %s" % (
-            f_ms, f_ms / float(np.mean(n_ms)), grad["pulay_forces"]["kernels_ms"]))
+        ms, kern = time_op(lambda: sysm.pulay_forces(D, Q, v, precision=prec, out=F))
+        grad["pulay_forces"] = {"ms": round(ms, 3), "vs_density": round(ms / n_mean, 3), "kernels_ms": kern}
+        log("local Pulay forces: %.2f ms (%.2fx the density alone); kernels: %s" % (ms, ms / n_mean, kern))
         del Q, F
 
     cpu = None

@@ -238,6 +238,23 @@ nao_status nao_integrate_h_gga(nao_system sys, const double* v, const double* a,
                                nao_precision precision, double* H, nao_memspace H_space);
 
 /* ---------------------------------------------------------------------------------------
+ * Kohn-Sham Hamiltonian with the kinetic term: eq. H_int_aims with h_KS acting on phi_j as
+ * t + v, t = -1/2 lap the non-relativistic kinetic operator, symmetrised in i and j, plus the
+ * optional vector-field term of nao_integrate_h_gga:
+ *   H_ij = sum_p w_p [ v_p phi_i phi_j + (phi_i t phi_j + phi_j t phi_i) / 2
+ *                      + a_p . (grad phi_i phi_j + phi_i grad phi_j) ]  at r_p.
+ * Batch by batch as eq. batch_matrix_mult in its symmetric rank-2k form, K = Phi and
+ * L = (w v / 2) Phi - (w / 4) lap Phi + (w a) . grad Phi, H_b = K^T L + L^T K.  lap phi =
+ * (R'' + 2 R'/r - l(l+1) R / r^2) Y_lm, taken from the radial spline's own first and second
+ * derivatives; zero where phi is cut off and for |r - R_A| <= rmin.  v [n_points] and
+ * a [n_points][3] (nullable: no field) in caller point order, both in in_space; H as for
+ * nao_integrate_h.  precision: NAO_FP64 or NAO_FP32.  Needs device scratch for one L value per
+ * basis value of a block (as much as the basis scratch).
+ * ------------------------------------------------------------------------------------- */
+nao_status nao_integrate_h_ks(nao_system sys, const double* v, const double* a, nao_memspace in_space,
+                              nao_precision precision, double* H, nao_memspace H_space);
+
+/* ---------------------------------------------------------------------------------------
  * Density and its gradient at every point, grad n(r_p) = 2 sum_ij grad phi_i(r_p) D_ij phi_j(r_p)
  * for symmetric D (the density gradients the paper names beside eq. Density and in the
  * subsection "Density and Density Derivatives, Force and Stress Tensor Components"), batch by

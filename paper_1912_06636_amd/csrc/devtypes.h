@@ -100,8 +100,9 @@ enum Mode { MODE_FP64 = 0, MODE_FP32 = 1, MODE_BF16X3 = 2, MODE_BF16X6 = 3 };
 // spline_lds: doubles of spline table to stage in LDS (0 = read it through the cache); it must
 // cover the largest table of the systems in the segment list.
 // extra: also write, to the segments' gphi, the gradient of every basis value (EXTRA_GRAD, 3 per
-// value) or L = (w v / 2) phi + (w a) . grad phi (EXTRA_GGA_L, 1 per value; needs wv and wa).
-enum BasisExtra { EXTRA_NONE = 0, EXTRA_GRAD = 1, EXTRA_GGA_L = 2 };
+// value), L = (w v / 2) phi + (w a) . grad phi (EXTRA_GGA_L, 1 per value; needs wv and wa) or
+// L = (w v / 2) phi - (w / 4) lap phi [+ (w a) . grad phi when wa is set] (EXTRA_KS_L, 1 per value).
+enum BasisExtra { EXTRA_NONE = 0, EXTRA_GRAD = 1, EXTRA_GGA_L = 2, EXTRA_KS_L = 3 };
 hipError_t launch_basis(const DevSeg* segs_dev, int n_segs, int64_t n_units, int spline_lds, bool fp32_out,
                         hipStream_t st, int64_t max_grid = 0, int extra = EXTRA_NONE);
 // h_tile: 64, or 128 for the wide FP64/FP32 kernels (items then index 128-wide tiles).

@@ -202,8 +202,10 @@ __global__ __launch_bounds__(256) void basis_kernel(const DevSeg* __restrict__ s
         if (SPLINE_LDS || staged) __syncthreads();
         gp<T> __restrict__ out = gptr(static_cast<T*>(sg.phi) + u.out_offset);
         // EX = EXTRA_GRAD: 3 gradient values per basis value; EX = EXTRA_GGA_L: L = (w v / 2) phi +
-        // (w a) . grad phi, one per basis value; same element order as the basis values
-        constexpr bool GRAD = EX == EXTRA_GRAD, GGA = EX == EXTRA_GGA_L;
+        // (w a) . grad phi, one per basis value; EX = EXTRA_KS_L: L = (w v / 2) phi - (w / 4) lap phi
+        // (+ (w a) . grad phi when the segment has a field); same element order as the basis values
+        constexpr bool GRAD = EX == EXTRA_GRAD, GGA = EX == EXTRA_GGA_L, KS = EX == EXTRA_KS_L;
+        const bool field = GGA || (KS && sg.wa != nullptr);  // uniform
         constexpr int XW = GRAD ? 3 : 1;  // extra values per basis value
         gp<T> __restrict__ gout = EX != EXTRA_NONE ? gptr(static_cast<T*>(sg.gphi) + XW * u.out_offset) : nullptr;
         const int64_t npairs = (int64_t)u.n_points * na;
@@ -260,7 +262,7 @@ __global__ __launch_bounds__(256) void basis_kernel(const DevSeg* __restrict__ s
                     const double rc2 = ST ? s_par[j][1] : rpar[4 * rr + 1];
                     const double idel = ST ? s_par[j][2] : rpar[4 * rr + 2];
                     const double lnmin = ST ? s_par[j][3] : rpar[4 * rr + 3];
-                    double R = 0.0, dR = 0.0;
+                    double R = 0.0, dR = 0.0, dS = 0.0, d2S = 0.0;
                     if (d2 < rc2) {
                         double t = r > rmin ? (lnr - lnmin) * idel : 0.0;
                         t = fmin(fmax(t, 0.0), tmax);
@@ -277,34 +279,47 @@ __global__ __launch_bounds__(256) void basis_kernel(const DevSeg* __restrict__ s
                         R = c0 + w * (c1 + w * (c2 + w * c3));
                         // dR/dr = dR/dw dt/dr with dt/dr = 1 / (r Delta); the clamped part r <= rmin is constant
                         if (EX != EXTRA_NONE && r > rmin) dR = (c1 + w * (2.0 * c2 + 3.0 * c3 * w)) * idel / r;
+                        if (KS) {
+                            dS = c1 + w * (2.0 * c2 + 3.0 * c3 * w);  // dR/dt
+                            d2S = 2.0 * c2 + 6.0 * c3 * w;           // d2R/dt2
+                        }
                     }
                     if (EX != EXTRA_NONE) {
                         // grad phi = R'(r) u Y + (R / r) (G - u (u . G)), G = dY/du; zero where the
                         // function is cut off or r <= rmin
                         const bool live = d2 < rc2 && r > rmin;
                         const double ir = live ? 1.0 / r : 0.0;
-                        double hwv = 0.0, wax = 0.0, way = 0.0, waz = 0.0;
-                        if (GGA) {
-                            hwv = 0.5 * gptr(sg.wv)[p];
+                        double hwv = 0.0, wax = 0.0, way = 0.0, waz = 0.0, qw = 0.0;
+                        if (GGA || KS) hwv = 0.5 * gptr(sg.wv)[p];
+                        if (field) {
                             gp<const double> wa = gptr(sg.wa) + 3 * p;
                             wax = wa[0], way = wa[1], waz = wa[2];
                         }
+                        // lap phi = (S''/Delta^2 + S'/Delta - l(l+1) S) Y / r^2 in the spline variable
+                        double lap = 0.0;
+                        if (KS) {
+                            qw = 0.25 * gptr(S->pw)[p];
+                            lap = live ? ((d2S * idel + dS) * idel - (double)(l * (l + 1)) * R) * ir * ir : 0.0;
+                        }
                         for (int f = 0; f < 2 * l + 1; ++f) {
                             const int lm = l * l + f;
-                            double gv[3];
-                            ylm_grad_one(lm, ux, uy, uz, gv);
-                            const double ug = (ux * gv[0] + uy * gv[1]) + uz * gv[2];
                             const double yv = Y[lm];
-                            const double g0 = live ? dR * ux * yv + R * ir * (gv[0] - ux * ug) : 0.0;
-                            const double g1 = live ? dR * uy * yv + R * ir * (gv[1] - uy * ug) : 0.0;
-                            const double g2 = live ? dR * uz * yv + R * ir * (gv[2] - uz * ug) : 0.0;
+                            double g0 = 0.0, g1 = 0.0, g2 = 0.0;
+                            if (GRAD || field) {
+                                double gv[3];
+                                ylm_grad_one(lm, ux, uy, uz, gv);
+                                const double ug = (ux * gv[0] + uy * gv[1]) + uz * gv[2];
+                                g0 = live ? dR * ux * yv + R * ir * (gv[0] - ux * ug) : 0.0;
+                                g1 = live ? dR * uy * yv + R * ir * (gv[1] - uy * ug) : 0.0;
+                                g2 = live ? dR * uz * yv + R * ir * (gv[2] - uz * ug) : 0.0;
+                            }
                             if (GRAD) {
                                 gp<T> dst = grow + 3 * (int64_t)(col + f);
                                 dst[0] = T(g0);
                                 dst[1] = T(g1);
                                 dst[2] = T(g2);
                             } else {
-                                grow[col + f] = T(hwv * (R * yv) + ((wax * g0 + way * g1) + waz * g2));
+                                grow[col + f] = T((hwv * (R * yv) - qw * (lap * yv)) + ((wax * g0 + way * g1) + waz * g2));
                             }
                         }
                     }
@@ -363,7 +378,8 @@ hipError_t launch_basis(const DevSeg* segs_dev, int n_segs, int64_t n_units, int
 {
     if (n_units <= 0 || n_segs <= 0) return hipSuccess;
     if (n_units > 0x7ffffff0 || spline_lds < 0 || spline_lds > MAX_SPLINE_LDS) return hipErrorInvalidValue;
-    if (extra != EXTRA_NONE && extra != EXTRA_GRAD && extra != EXTRA_GGA_L) return hipErrorInvalidValue;
+    if (extra != EXTRA_NONE && extra != EXTRA_GRAD && extra != EXTRA_GGA_L && extra != EXTRA_KS_L)
+        return hipErrorInvalidValue;
     const dim3 g(grid_for(n_units, max_grid)), b(256);
     const bool staged = spline_lds > 0;
     const size_t lds = (size_t)spline_lds * sizeof(double);
@@ -379,7 +395,9 @@ hipError_t launch_basis(const DevSeg* segs_dev, int n_segs, int64_t n_units, int
         reinterpret_cast<const void*>(&basis_kernel<TT, true, EXTRA_GRAD>),                                      \
         reinterpret_cast<const void*>(&basis_kernel<TT, false, EXTRA_GRAD>),                                     \
         reinterpret_cast<const void*>(&basis_kernel<TT, true, EXTRA_GGA_L>),                                     \
-        reinterpret_cast<const void*>(&basis_kernel<TT, false, EXTRA_GGA_L>)
+        reinterpret_cast<const void*>(&basis_kernel<TT, false, EXTRA_GGA_L>),                                    \
+        reinterpret_cast<const void*>(&basis_kernel<TT, true, EXTRA_KS_L>),                                      \
+        reinterpret_cast<const void*>(&basis_kernel<TT, false, EXTRA_KS_L>)
         const void* fns[] = {NAO_BASIS_FNS(float), NAO_BASIS_FNS(double)};
 #undef NAO_BASIS_FNS
         for (const void* f : fns) {
@@ -397,6 +415,7 @@ hipError_t launch_basis(const DevSeg* segs_dev, int n_segs, int64_t n_units, int
     do {                                                              \
         if (extra == EXTRA_GRAD) NAO_BASIS_LAUNCH(TT, EXTRA_GRAD);    \
         else if (extra == EXTRA_GGA_L) NAO_BASIS_LAUNCH(TT, EXTRA_GGA_L); \
+        else if (extra == EXTRA_KS_L) NAO_BASIS_LAUNCH(TT, EXTRA_KS_L); \
         else NAO_BASIS_LAUNCH(TT, EXTRA_NONE);                        \
     } while (0)
     if (fp32_out) NAO_BASIS_EXTRA(float);

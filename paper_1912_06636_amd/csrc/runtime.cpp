@@ -1426,31 +1426,33 @@ static nao_status ensure_gscratch(nao_system s, int per_value)
     return st;
 }
 
-nao_status nao_integrate_h_gga(nao_system s, const double* v, const double* a, nao_memspace in_space,
-                               nao_precision prec, double* H, nao_memspace H_space)
+// H = K^T L + L^T K over the upper-triangle tile pairs, L written by the basis launch in mode
+// `extra` (EXTRA_GGA_L, or EXTRA_KS_L with an optional field a), then mirrored.
+static nao_status integrate_h_with_l(nao_system s, const double* v, const double* a, nao_memspace in_space,
+                                     nao_precision prec, double* H, nao_memspace H_space, int extra)
 {
-    if (!s) return (g_thread_error = "system is NULL", NAO_ERR_INVALID_ARG);
     nao_ctx c = s->ctx;
-    nao_status st = check_ctx(c);
-    if (st != NAO_OK) return st;
-    if (prec != NAO_FP64 && prec != NAO_FP32)
-        return (set_err(c, "the Hamiltonian with a vector field runs in FP64 or FP32"), NAO_ERR_INVALID_ARG);
+    const bool ks = extra == EXTRA_KS_L;
     const int64_t n = s->n_points, nb = s->basis.n_basis;
-    if (!H || (n > 0 && (!v || !a))) return (set_err(c, "NULL v, a or H"), NAO_ERR_INVALID_ARG);
+    if (!H || (n > 0 && (!v || (!ks && !a)))) return (set_err(c, "NULL v, a or H"), NAO_ERR_INVALID_ARG);
     if ((in_space != NAO_MEM_HOST && in_space != NAO_MEM_DEVICE) || (H_space != NAO_MEM_HOST && H_space != NAO_MEM_DEVICE))
         return (set_err(c, "bad memspace"), NAO_ERR_INVALID_ARG);
+    nao_status st;
     if ((st = ensure_gscratch(s, 1)) != NAO_OK) return st;  // L: one value per basis value
+    const bool has_a = a != nullptr && n > 0;
     const double* vd = v;
     const double* ad = a;
     if (in_space == NAO_MEM_HOST && n > 0) {
         if ((st = ensure(c, s->d_v, n * sizeof(double))) != NAO_OK) return st;
-        if ((st = ensure(c, s->d_a, 3 * n * sizeof(double))) != NAO_OK) return st;
         HIP_TRY(c, hipMemcpyAsync(s->d_v.p, v, n * sizeof(double), hipMemcpyHostToDevice, c->stream));
-        HIP_TRY(c, hipMemcpyAsync(s->d_a.p, a, 3 * n * sizeof(double), hipMemcpyHostToDevice, c->stream));
         vd = s->d_v.as<double>();
-        ad = s->d_a.as<double>();
+        if (has_a) {
+            if ((st = ensure(c, s->d_a, 3 * n * sizeof(double))) != NAO_OK) return st;
+            HIP_TRY(c, hipMemcpyAsync(s->d_a.p, a, 3 * n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+            ad = s->d_a.as<double>();
+        }
     }
-    if ((st = ensure(c, s->d_wa, std::max<int64_t>(1, 3 * n) * sizeof(double))) != NAO_OK) return st;
+    if (has_a && (st = ensure(c, s->d_wa, std::max<int64_t>(1, 3 * n) * sizeof(double))) != NAO_OK) return st;
     double* Hd = H;
     if (H_space == NAO_MEM_HOST) {
         if ((st = ensure(c, s->d_H, std::max<int64_t>(1, nb * nb) * sizeof(double))) != NAO_OK) return st;
@@ -1458,14 +1460,15 @@ nao_status nao_integrate_h_gga(nao_system s, const double* v, const double* a, n
     }
     LAUNCH(c, "fill", launch_fill(Hd, nb * nb, 0.0, c->stream));
     LAUNCH(c, "wv", launch_wv(s->d_pw.as<double>(), s->d_perm.as<int32_t>(), vd, s->d_wv.as<double>(), n, c->stream));
-    LAUNCH(c, "wa", launch_wa(s->d_pw.as<double>(), s->d_perm.as<int32_t>(), ad, s->d_wa.as<double>(), n, c->stream));
+    if (has_a)
+        LAUNCH(c, "wa", launch_wa(s->d_pw.as<double>(), s->d_perm.as<int32_t>(), ad, s->d_wa.as<double>(), n, c->stream));
     const Mode mode = exec_mode(c, prec);
     const bool f32 = prec != NAO_FP64;
     std::vector<DevSeg> segs;
     for (const Block& b : s->blocks) {
         DevSeg g = make_seg(s, b, true, false);
         g.wv = s->d_wv.as<double>();
-        g.wa = s->d_wa.as<double>();
+        g.wa = has_a ? s->d_wa.as<double>() : nullptr;
         g.H = Hd;
         g.gphi = c->gscratch;
         segs.push_back(g);
@@ -1474,10 +1477,11 @@ nao_status nao_integrate_h_gga(nao_system s, const double* v, const double* a, n
         HIP_TRY(c, hipMemcpyAsync(s->d_segs.p, segs.data(), segs.size() * sizeof(DevSeg), hipMemcpyHostToDevice,
                                   c->stream));
         DevSeg* dseg = s->d_segs.as<DevSeg>();
+        const char* bname = ks ? (f32 ? "basis_ks_f32" : "basis_ks_f64") : (f32 ? "basis_gga_f32" : "basis_gga_f64");
+        const char* hname = ks ? (f32 ? "hks_f32" : "hks_f64") : (f32 ? "hgga_f32" : "hgga_f64");
         for (size_t k = 0; k < segs.size(); ++k) {
-            LAUNCH(c, f32 ? "basis_gga_f32" : "basis_gga_f64",
-                   launch_basis(dseg + k, 1, segs[k].unit_count, s->spline_lds, f32, c->stream, 0, EXTRA_GGA_L));
-            LAUNCH(c, f32 ? "hgga_f32" : "hgga_f64", launch_h_gga(mode, dseg + k, 1, segs[k].item_count, c->stream));
+            LAUNCH(c, bname, launch_basis(dseg + k, 1, segs[k].unit_count, s->spline_lds, f32, c->stream, 0, extra));
+            LAUNCH(c, hname, launch_h_gga(mode, dseg + k, 1, segs[k].item_count, c->stream));
         }
     }
     LAUNCH(c, "mirror", launch_mirror(Hd, nb, c->stream));
@@ -1487,6 +1491,30 @@ nao_status nao_integrate_h_gga(nao_system s, const double* v, const double* a, n
     }
     if (in_space == NAO_MEM_HOST) HIP_TRY(c, hipStreamSynchronize(c->stream));
     return NAO_OK;
+}
+
+nao_status nao_integrate_h_gga(nao_system s, const double* v, const double* a, nao_memspace in_space,
+                               nao_precision prec, double* H, nao_memspace H_space)
+{
+    if (!s) return (g_thread_error = "system is NULL", NAO_ERR_INVALID_ARG);
+    nao_ctx c = s->ctx;
+    nao_status st = check_ctx(c);
+    if (st != NAO_OK) return st;
+    if (prec != NAO_FP64 && prec != NAO_FP32)
+        return (set_err(c, "the Hamiltonian with a vector field runs in FP64 or FP32"), NAO_ERR_INVALID_ARG);
+    return integrate_h_with_l(s, v, a, in_space, prec, H, H_space, EXTRA_GGA_L);
+}
+
+nao_status nao_integrate_h_ks(nao_system s, const double* v, const double* a, nao_memspace in_space,
+                              nao_precision prec, double* H, nao_memspace H_space)
+{
+    if (!s) return (g_thread_error = "system is NULL", NAO_ERR_INVALID_ARG);
+    nao_ctx c = s->ctx;
+    nao_status st = check_ctx(c);
+    if (st != NAO_OK) return st;
+    if (prec != NAO_FP64 && prec != NAO_FP32)
+        return (set_err(c, "the Kohn-Sham Hamiltonian runs in FP64 or FP32"), NAO_ERR_INVALID_ARG);
+    return integrate_h_with_l(s, v, a, in_space, prec, H, H_space, EXTRA_KS_L);
 }
 
 nao_status nao_update_density_gradient(nao_system s, const double* D, nao_memspace D_space, nao_precision prec,

@@ -85,6 +85,7 @@ _sig("nao_integrate_h", _S, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_
 _sig("nao_update_density", _S, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int, _c_dp)
 _sig("nao_update_density_gradient", _S, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_int)
 _sig("nao_pulay_forces", _S, _vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int)
+_sig("nao_integrate_h_ks", _S, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int)
 _sig("nao_integrate_h_gga", _S, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int)
 _sig("nao_system_destroy", None, _vp)
 _sig("nao_run_many", _S, _vp, ctypes.POINTER(Work), ctypes.c_int64, ctypes.c_int, ctypes.c_uint32)
@@ -105,7 +106,7 @@ EXPORTED = [
     "nao_ctx_synchronize", "nao_ctx_memory", "nao_ctx_profile", "nao_ctx_profile_read", "nao_plan_create", "nao_plan_info", "nao_plan_get_batches",
     "nao_plan_destroy", "nao_build_batches", "nao_system_set_group_max", "nao_system_set_h_tile", "nao_system_autotune", "nao_system_info", "nao_get_batches",
     "nao_system_work", "nao_eval_basis", "nao_integrate_h", "nao_update_density", "nao_update_density_gradient", "nao_integrate_h_gga",
-    "nao_pulay_forces",
+    "nao_pulay_forces", "nao_integrate_h_ks",
     "nao_system_destroy",
     "nao_run_many", "nao_server_create", "nao_server_open_session", "nao_server_close_session",
     "nao_server_session_info", "nao_server_submit", "nao_server_step", "nao_server_poll", "nao_server_result",
@@ -384,6 +385,21 @@ class System:
             out = np.empty((self.n_basis, self.n_basis), np.float64)
         ph, sh, kh = _ptr_space(out)
         _check(_lib.nao_integrate_h_gga(self.handle, pv, pa, sv, PRECISIONS[precision], ph, sh), self.ctx.handle)
+        return out
+
+    def integrate_h_ks(self, v, a=None, precision="fp64", out=None):
+        """nao_integrate_h_ks: H with the kinetic term, the local potential v and (a not None)
+        the vector field a [n_points, 3]."""
+        pv, sv, kv = _ptr_space(v)
+        pa, sa = None, sv
+        if a is not None:
+            pa, sa, ka = _ptr_space(a)
+        if sv != sa:
+            raise ValueError("v and a must be in the same memory space")
+        if out is None:
+            out = np.empty((self.n_basis, self.n_basis), np.float64)
+        ph, sh, kh = _ptr_space(out)
+        _check(_lib.nao_integrate_h_ks(self.handle, pv, pa, sv, PRECISIONS[precision], ph, sh), self.ctx.handle)
         return out
 
     def update_density_gradient(self, D, precision="fp64", out=None, out_grad=None):

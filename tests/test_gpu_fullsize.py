@@ -188,3 +188,21 @@ def test_fp64_forces_sampled_against_oracle(nao, cfg):
     e = float(np.max(np.abs(F[atoms] - ref))) / scale
     say("config", cfg, "sampled e_F %.3e over atoms %s" % (e, atoms))
     assert e <= 1e-12
+
+
+@pytest.mark.parametrize("cfg", [2, 4])
+def test_fp64_ks_hamiltonian_sampled_against_oracle(nao, cfg):
+    say("full-size kohn-sham hamiltonian vs oracle samples, config", cfg)
+    w, B = full(cfg)
+    ctx = nao.Context(0)
+    s = nao.build_batches(ctx, w["basis"], w["xyz"], w["w"], w["max_batch"])
+    H = s.integrate_h_ks(w["v"])
+    s.close()
+    ctx.close()
+    assert np.array_equal(H, H.T)
+    pairs = sample_pairs(H, 10, 80 + cfg)
+    ref = oi.hamiltonian_ks_entries(B, w["xyz"], w["w"], w["v"], None, pairs)
+    got = np.array([H[i, j] for i, j in pairs])
+    e = float(np.max(np.abs(got - ref))) / float(np.max(np.abs(H)))
+    say("config", cfg, "sampled e_H %.3e over %d pairs" % (e, len(pairs)))
+    assert e <= 1e-12
