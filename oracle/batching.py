@@ -2,7 +2,8 @@
 
 Section "Grid Partitioning": the integration points are split into mutually
 disjoint, spatially compact batches of at most a target size ("batch size").
-The paper uses a grid-adapted cut-plane method; this build uses an octree.
+The paper uses a grid-adapted cut-plane method (cutplane_batches below, with the
+reading stated there); the octree is the default of this build.
 Reading (octree definition):
 
 * root box = per-axis [min, max] of all points;
@@ -62,6 +63,45 @@ def octree_batches(xyz, max_batch: int):
                 children.append((sel, np.where(bits, mid, lo), np.where(bits, hi, mid), depth + 1))
             # pre-order: push in reverse so that octant 0 is processed first
             stack.extend(reversed(children))
+    perm = np.concatenate(leaves) if leaves else np.zeros(0, dtype=np.int64)
+    batch_ptr = np.zeros(len(leaves) + 1, dtype=np.int64)
+    batch_ptr[1:] = np.cumsum([len(x) for x in leaves])
+    return perm, batch_ptr
+
+
+def cutplane_batches(xyz, max_batch: int):
+    """Return (perm, batch_ptr) of the grid-adapted cut-plane partition (Section "Grid
+    Partitioning": the point set is cut by planes, again and again, until every subset holds
+    at most the batch size).  The paper gives no further detail; reading used here:
+
+    * a set S with |S| <= max_batch is a batch, its indices ascending;
+    * otherwise it is meant to end as k = ceil(|S| / max_batch) batches; the plane is normal
+      to the axis d of largest extent max - min of S's coordinates (ties: lowest axis) and is
+      placed at a quantile of the points (the grid adaptation): with S ordered by
+      (coordinate d, point index) ascending, the first floor(|S| floor(k/2) / k) points form
+      the lower side, the rest the upper side;
+    * the lower side is processed first (depth-first pre-order); batches are numbered in
+      emission order.
+    Every cut splits the targeted k batches into floor(k/2) and ceil(k/2), and each side fits
+    them, so every batch holds at most max_batch points and about |P| / ceil(|P| / max_batch)."""
+    xyz = np.asarray(xyz, dtype=np.float64).reshape(-1, 3)
+    n = len(xyz)
+    leaves = []
+    stack = [np.arange(n, dtype=np.int64)] if n > 0 else []
+    while stack:
+        idx = stack.pop()
+        m = len(idx)
+        if m <= max_batch:
+            leaves.append(np.sort(idx))
+            continue
+        k = -(-m // max_batch)
+        p = xyz[idx]
+        ext = p.max(axis=0) - p.min(axis=0)
+        d = int(np.argmax(ext))  # first maximum: lowest axis on ties
+        order = np.lexsort((idx, p[:, d]))
+        n_lo = (m * (k // 2)) // k
+        stack.append(idx[order[n_lo:]])
+        stack.append(idx[order[:n_lo]])  # popped first
     perm = np.concatenate(leaves) if leaves else np.zeros(0, dtype=np.int64)
     batch_ptr = np.zeros(len(leaves) + 1, dtype=np.int64)
     batch_ptr[1:] = np.cumsum([len(x) for x in leaves])
