@@ -49,7 +49,7 @@ WORKLOADS = {
 }
 
 
-def measured_traffic(workload, prec, h_tile, group_max, kernel):
+def measured_traffic(workload, prec, h_tile, group_max, kernel, batcher="octree", max_batch=256):
     """Counter-derived HBM bytes per launch of `kernel`, or None when the kernel source or the
     launch configuration differ from the ones the counters were taken on."""
     import hashlib
@@ -57,7 +57,7 @@ def measured_traffic(workload, prec, h_tile, group_max, kernel):
         sha = hashlib.sha256(f.read()).hexdigest()
     t = TRAFFIC
     if (t["sha256"] != sha or t["workload"] != workload or t["precision"] != prec or t["h_tile"] != h_tile
-            or t["group_max"] != group_max):
+            or t["group_max"] != group_max or batcher != "octree" or max_batch != 256):
         return None
     return t["bytes_per_launch"].get(kernel)
 
@@ -201,6 +201,9 @@ def main():
     ap.add_argument("--workload", default="slab375", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="fp64")
     ap.add_argument("--group-max", type=int, default=256)
+    ap.add_argument("--batcher", default="octree", choices=["octree", "cutplane"],
+                    help="batching method (the workload's own is the octree)")
+    ap.add_argument("--max-batch", type=int, default=0, help="batch size; 0 = the workload's (256)")
     ap.add_argument("--h-tile", type=int, default=0, help="Hamiltonian tile width (64 or 128); 0 = autotune")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip timing the plain FP64 per-batch path")
@@ -230,12 +233,14 @@ def main():
     stream = torch.cuda.Stream(device=dev)
     ctx = nao.Context(0, stream=stream.cuda_stream)
     t0 = time.time()
-    sysm = nao.build_batches(ctx, work["basis"], work["xyz"], work["w"], work["max_batch"])
+    max_batch = args.max_batch or work["max_batch"]
+    sysm = nao.build_batches(ctx, work["basis"], work["xyz"], work["w"], max_batch, batcher=args.batcher)
     if args.group_max != 256:
         sysm.set_group_max(args.group_max)
     if args.h_tile:
         sysm.set_h_tile(args.h_tile)
-    log("system built in %.1f s: %d batches, N_b=%d" % (time.time() - t0, sysm.n_batches, sysm.n_basis))
+    log("system built in %.1f s: %d %s batches (max %d points), N_b=%d" % (
+        time.time() - t0, sysm.n_batches, args.batcher, max_batch, sysm.n_basis))
     perm, bp, lp, li, Bsz, msz = batch_measures(sysm)
     U = float(np.sum(Bsz * msz * msz))
     sum_Bm = float(np.sum(Bsz * msz))
@@ -311,7 +316,8 @@ def main():
         peak = PEAK.get(prec, PEAK["fp64"])
         roofline = {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 3), "peak": peak,
                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-                    "traffic": measured_traffic(args.workload, prec, h_tile_used, group_max_used, dom),
+                    "traffic": measured_traffic(args.workload, prec, h_tile_used, group_max_used, dom,
+                                                args.batcher, max_batch),
                     "launches": launches, "avg_launch_ms": round(tot_ms / launches, 4),
                     "flops_per_launch": credit[dom] / launches}
 
@@ -405,6 +411,8 @@ def main():
         "config": {"workload": args.workload, "description": desc, "n_points": int(sysm.n_points),
                    "n_basis": int(sysm.n_basis), "n_batches": int(sysm.n_batches), "units_per_op": U,
                    "group_max": args.group_max, "h_tile": args.h_tile, "precision": prec,
+                   "batcher": args.batcher, "max_batch": max_batch,
+                   "mean_batch": round(float(sysm.n_points) / max(1, sysm.n_batches), 2),
                    "autotuned": tuned},
         "latency_ms": {"p50": round(float(np.percentile(step_ms, 50)), 3),
                        "p99": round(float(np.percentile(step_ms, 99)), 3)},

@@ -140,6 +140,21 @@ nao_status nao_ctx_profile_read(nao_ctx ctx, int32_t max_entries, char* names, i
  * ------------------------------------------------------------------------------------- */
 nao_status nao_plan_create(const nao_basis_desc* basis, int64_t n_points, const double* point_xyz,
                            int32_t max_batch, nao_plan* out);
+
+/* Batching method of nao_plan_create_ex / nao_build_batches_ex.
+ * NAO_BATCH_OCTREE: the octree above (what nao_plan_create and nao_build_batches use).
+ * NAO_BATCH_CUTPLANE: the grid-adapted cut-plane partition the paper uses (Section "Grid
+ * Partitioning": the point set is cut by planes until every subset holds at most the batch
+ * size).  Definition: a set S with |S| <= max_batch is a batch, indices ascending; otherwise,
+ * with k = ceil(|S| / max_batch), the plane is normal to the axis of largest extent
+ * (max - min of S's coordinates, FP64; ties: lowest axis) and S, ordered by (coordinate on
+ * that axis, point index), gives its first floor(|S| floor(k/2) / k) points to the lower side,
+ * the rest to the upper side; the lower side is processed first and batches are numbered in
+ * emission order.  Gives exactly ceil(n_points / max_batch) batches (max_batch >= 2) of nearly
+ * equal size.  Bit-exact like the octree; relevance and lists as above. */
+typedef enum { NAO_BATCH_OCTREE = 0, NAO_BATCH_CUTPLANE = 1 } nao_batcher;
+nao_status nao_plan_create_ex(const nao_basis_desc* basis, int64_t n_points, const double* point_xyz,
+                              int32_t max_batch, nao_batcher batcher, nao_plan* out);
 nao_status nao_plan_info(nao_plan plan, int64_t* n_basis, int64_t* n_batches, int64_t* n_list);
 /* perm [n_points] (batch b = points perm[batch_ptr[b] .. batch_ptr[b+1]-1]),
  * batch_ptr [n_batches+1], basis_ptr [n_batches+1], basis_idx [n_list]; any may be NULL. */
@@ -159,8 +174,12 @@ void nao_plan_destroy(nao_plan plan);
 nao_status nao_build_batches(nao_ctx ctx, const nao_basis_desc* basis, int64_t n_points,
                              const double* point_xyz, const double* point_w, int32_t max_batch,
                              nao_system* out);
+/* nao_build_batches with the batching method chosen (nao_batcher). */
+nao_status nao_build_batches_ex(nao_ctx ctx, const nao_basis_desc* basis, int64_t n_points,
+                                const double* point_xyz, const double* point_w, int32_t max_batch,
+                                nao_batcher batcher, nao_system* out);
 /* Change the execution-group size (in points, 16..256; default 256) of a system; 0 runs
- * every octree batch as its own unit (no packing).  Results change only by floating-point
+ * every batch as its own unit (no packing).  Results change only by floating-point
  * summation order. */
 nao_status nao_system_set_group_max(nao_system sys, int32_t group_max);
 /* Tile width (64 or 128 basis functions) of the Hamiltonian kernel for this system; wider

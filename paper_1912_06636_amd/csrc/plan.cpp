@@ -154,6 +154,75 @@ void octree_batches(const double* xyz, int64_t n, int32_t max_batch, std::vector
     b.node(0, n, lo, hi, 0);
 }
 
+namespace {
+
+// Grid-adapted cut-plane partition: a range with more than max_batch points is meant to end
+// as k = ceil(count / max_batch) batches; it is cut by the plane normal to its axis of largest
+// extent at the point quantile floor(count floor(k/2) / k) under the order (coordinate, index),
+// the lower side first.  The lower set is unique under that total order, so nth_element gives
+// the same partition as a full sort.
+struct CutPlaneBuilder {
+    const double* xyz;
+    int32_t max_batch;
+    std::vector<int64_t>& perm;
+    std::vector<int64_t>& batch_ptr;
+
+    void node(int64_t lo, int64_t hi)
+    {
+        const int64_t m = hi - lo;
+        if (m <= max_batch) {
+            std::sort(perm.begin() + lo, perm.begin() + hi);
+            batch_ptr.push_back(hi);
+            return;
+        }
+        const int64_t k = (m + max_batch - 1) / max_batch;
+        double mn[3], mx[3];
+        for (int d = 0; d < 3; ++d) mn[d] = mx[d] = xyz[3 * perm[lo] + d];
+        for (int64_t q = lo + 1; q < hi; ++q)
+            for (int d = 0; d < 3; ++d) {
+                const double x = xyz[3 * perm[q] + d];
+                if (x < mn[d]) mn[d] = x;
+                if (x > mx[d]) mx[d] = x;
+            }
+        int d = 0;
+        double best = mx[0] - mn[0];
+        for (int e = 1; e < 3; ++e)
+            if (mx[e] - mn[e] > best) {
+                best = mx[e] - mn[e];
+                d = e;
+            }
+        const int64_t n_lo = (m * (k / 2)) / k;
+        const double* X = xyz;
+        std::nth_element(perm.begin() + lo, perm.begin() + lo + n_lo, perm.begin() + hi,
+                         [X, d](int64_t a, int64_t b) {
+                             const double xa = X[3 * a + d], xb = X[3 * b + d];
+                             return xa < xb || (xa == xb && a < b);
+                         });
+        node(lo, lo + n_lo);
+        node(lo + n_lo, hi);
+    }
+};
+
+}  // namespace
+
+void cutplane_batches(const double* xyz, int64_t n, int32_t max_batch, std::vector<int64_t>& perm,
+                      std::vector<int64_t>& batch_ptr)
+{
+    perm.resize(n);
+    for (int64_t k = 0; k < n; ++k) perm[k] = k;
+    batch_ptr.assign(1, 0);
+    if (n == 0) return;
+    CutPlaneBuilder b{xyz, max_batch, perm, batch_ptr};
+    b.node(0, n);
+}
+
+void make_batches(int32_t batcher, const double* xyz, int64_t n, int32_t max_batch, std::vector<int64_t>& perm,
+                  std::vector<int64_t>& batch_ptr)
+{
+    if (batcher == NAO_BATCH_CUTPLANE) cutplane_batches(xyz, n, max_batch, perm, batch_ptr);
+    else octree_batches(xyz, n, max_batch, perm, batch_ptr);
+}
+
 // ------------------------------------------------------------------------------------------
 // relevance
 

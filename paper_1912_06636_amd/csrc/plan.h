@@ -36,6 +36,12 @@ std::string load_basis(const nao_basis_desc* d, HostBasis& out);
 // Octree batches (see nao.h): perm [n], batch_ptr [n_batches+1].
 void octree_batches(const double* xyz, int64_t n, int32_t max_batch, std::vector<int64_t>& perm,
                     std::vector<int64_t>& batch_ptr);
+// Grid-adapted cut-plane batches (see nao.h), same output form.
+void cutplane_batches(const double* xyz, int64_t n, int32_t max_batch, std::vector<int64_t>& perm,
+                      std::vector<int64_t>& batch_ptr);
+// Batches by the method nao_batcher names (NAO_BATCH_OCTREE or NAO_BATCH_CUTPLANE).
+void make_batches(int32_t batcher, const double* xyz, int64_t n, int32_t max_batch, std::vector<int64_t>& perm,
+                  std::vector<int64_t>& batch_ptr);
 
 // Relevant atoms of every batch (ascending), CSR.
 void relevant_atoms(const HostBasis& b, const double* xyz, const std::vector<int64_t>& perm,

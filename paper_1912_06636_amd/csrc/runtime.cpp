@@ -268,6 +268,7 @@ struct nao_system_s {
     HostBasis basis;
     int64_t n_points = 0;
     int32_t max_batch = 0;
+    int32_t batcher = NAO_BATCH_OCTREE;
     int32_t group_max = MAX_UNIT_POINTS;
     int32_t h_tile = TILE;  // width of the Hamiltonian kernel's tiles (64 or 128)
     std::vector<int64_t> perm, batch_ptr, atom_ptr;
@@ -945,8 +946,16 @@ static nao_status check_points(const double* xyz, int64_t n, int32_t max_batch, 
 nao_status nao_plan_create(const nao_basis_desc* basis, int64_t n_points, const double* point_xyz,
                            int32_t max_batch, nao_plan* out)
 {
+    return nao_plan_create_ex(basis, n_points, point_xyz, max_batch, NAO_BATCH_OCTREE, out);
+}
+
+nao_status nao_plan_create_ex(const nao_basis_desc* basis, int64_t n_points, const double* point_xyz,
+                              int32_t max_batch, nao_batcher batcher, nao_plan* out)
+{
     if (!out) return (g_thread_error = "out is NULL", NAO_ERR_INVALID_ARG);
     *out = nullptr;
+    if (batcher != NAO_BATCH_OCTREE && batcher != NAO_BATCH_CUTPLANE)
+        return (g_thread_error = "unknown batcher", NAO_ERR_INVALID_ARG);
     std::string why;
     nao_status st = check_points(point_xyz, n_points, max_batch, why);
     if (st != NAO_OK) return (g_thread_error = why, st);
@@ -959,7 +968,7 @@ nao_status nao_plan_create(const nao_basis_desc* basis, int64_t n_points, const 
             return NAO_ERR_INVALID_ARG;
         }
         p->n_points = n_points;
-        octree_batches(point_xyz, n_points, max_batch, p->perm, p->batch_ptr);
+        make_batches(batcher, point_xyz, n_points, max_batch, p->perm, p->batch_ptr);
         relevant_atoms(p->basis, point_xyz, p->perm, p->batch_ptr, p->atom_ptr, p->atoms);
         expand_lists(p->basis, p->atom_ptr, p->atoms, p->basis_ptr, p->basis_idx);
         *out = p;
@@ -1002,7 +1011,7 @@ static nao_status setup_system(nao_system s, const double* xyz, const double* w)
     nao_ctx c = s->ctx;
     const HostBasis& B = s->basis;
     const int64_t n = s->n_points;
-    octree_batches(xyz, n, s->max_batch, s->perm, s->batch_ptr);
+    make_batches(s->batcher, xyz, n, s->max_batch, s->perm, s->batch_ptr);
     relevant_atoms(B, xyz, s->perm, s->batch_ptr, s->atom_ptr, s->atoms);
     s->work_units = 0.0;
     for (size_t b = 0; b + 1 < s->batch_ptr.size(); ++b) {
@@ -1093,10 +1102,18 @@ static nao_status setup_system(nao_system s, const double* xyz, const double* w)
 nao_status nao_build_batches(nao_ctx c, const nao_basis_desc* basis, int64_t n_points, const double* point_xyz,
                              const double* point_w, int32_t max_batch, nao_system* out)
 {
+    return nao_build_batches_ex(c, basis, n_points, point_xyz, point_w, max_batch, NAO_BATCH_OCTREE, out);
+}
+
+nao_status nao_build_batches_ex(nao_ctx c, const nao_basis_desc* basis, int64_t n_points, const double* point_xyz,
+                                const double* point_w, int32_t max_batch, nao_batcher batcher, nao_system* out)
+{
     if (!out) return (set_err(c, "out is NULL"), NAO_ERR_INVALID_ARG);
     *out = nullptr;
     nao_status st = check_ctx(c);
     if (st != NAO_OK) return st;
+    if (batcher != NAO_BATCH_OCTREE && batcher != NAO_BATCH_CUTPLANE)
+        return (set_err(c, "unknown batcher"), NAO_ERR_INVALID_ARG);
     std::string why;
     if ((st = check_points(point_xyz, n_points, max_batch, why)) != NAO_OK) return (set_err(c, why), st);
     if (n_points > 0 && !point_w) return (set_err(c, "point_w is NULL"), NAO_ERR_INVALID_ARG);
@@ -1115,6 +1132,7 @@ nao_status nao_build_batches(nao_ctx c, const nao_basis_desc* basis, int64_t n_p
         }
         s->n_points = n_points;
         s->max_batch = max_batch;
+        s->batcher = batcher;
         st = setup_system(s, point_xyz, point_w);
     } catch (const std::bad_alloc&) {
         set_err(c, "host allocation failed");
@@ -1728,7 +1746,7 @@ void tune_save(const std::map<std::string, std::pair<int, int>>& c)
 }
 
 // Shape class of a system: device, precision, work-weighted mean list length and mean batch
-// size of its octree batches (both bucketed), batch-size limit.
+// size of its batches (both bucketed), batch-size limit.
 std::string tune_key(nao_system s, nao_precision prec)
 {
     hipDeviceProp_t prop;

@@ -69,11 +69,15 @@ _sig("nao_ctx_memory", _S, _vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(
 _sig("nao_ctx_profile", _S, _vp, ctypes.c_int)
 _sig("nao_ctx_profile_read", _S, _vp, ctypes.c_int32, ctypes.c_char_p, _c_i64p, _c_dp, _c_i32p)
 _sig("nao_plan_create", _S, ctypes.POINTER(BasisDesc), ctypes.c_int64, _c_dp, ctypes.c_int32, ctypes.POINTER(_vp))
+_sig("nao_plan_create_ex", _S, ctypes.POINTER(BasisDesc), ctypes.c_int64, _c_dp, ctypes.c_int32, ctypes.c_int,
+     ctypes.POINTER(_vp))
 _sig("nao_plan_info", _S, _vp, _c_i64p, _c_i64p, _c_i64p)
 _sig("nao_plan_get_batches", _S, _vp, _c_i64p, _c_i64p, _c_i64p, _c_i32p)
 _sig("nao_plan_destroy", None, _vp)
 _sig("nao_build_batches", _S, _vp, ctypes.POINTER(BasisDesc), ctypes.c_int64, _c_dp, _c_dp, ctypes.c_int32,
      ctypes.POINTER(_vp))
+_sig("nao_build_batches_ex", _S, _vp, ctypes.POINTER(BasisDesc), ctypes.c_int64, _c_dp, _c_dp, ctypes.c_int32,
+     ctypes.c_int, ctypes.POINTER(_vp))
 _sig("nao_system_set_group_max", _S, _vp, ctypes.c_int32)
 _sig("nao_system_set_h_tile", _S, _vp, ctypes.c_int32)
 _sig("nao_system_autotune", _S, _vp, ctypes.c_int, _vp, _vp, ctypes.c_int, ctypes.c_uint32, _c_i32p, _c_i32p, _c_dp)
@@ -106,7 +110,7 @@ EXPORTED = [
     "nao_ctx_synchronize", "nao_ctx_memory", "nao_ctx_profile", "nao_ctx_profile_read", "nao_plan_create", "nao_plan_info", "nao_plan_get_batches",
     "nao_plan_destroy", "nao_build_batches", "nao_system_set_group_max", "nao_system_set_h_tile", "nao_system_autotune", "nao_system_info", "nao_get_batches",
     "nao_system_work", "nao_eval_basis", "nao_integrate_h", "nao_update_density", "nao_update_density_gradient", "nao_integrate_h_gga",
-    "nao_pulay_forces", "nao_integrate_h_ks",
+    "nao_pulay_forces", "nao_integrate_h_ks", "nao_plan_create_ex", "nao_build_batches_ex",
     "nao_system_destroy",
     "nao_run_many", "nao_server_create", "nao_server_open_session", "nao_server_close_session",
     "nao_server_session_info", "nao_server_submit", "nao_server_step", "nao_server_poll", "nao_server_result",
@@ -172,12 +176,16 @@ def _ptr_space(x):
 # ---------------------------------------------------------------------------------------------
 # host-only planning
 
-def plan_create(basis, xyz, max_batch):
-    """nao_plan_create + nao_plan_get_batches: (perm, batch_ptr, basis_ptr, basis_idx)."""
+BATCHERS = {"octree": 0, "cutplane": 1}
+
+
+def plan_create(basis, xyz, max_batch, batcher="octree"):
+    """nao_plan_create_ex + nao_plan_get_batches: (perm, batch_ptr, basis_ptr, basis_idx)."""
     d = _Desc(basis)
     xyz = _f64(xyz).reshape(-1, 3)
     h = _vp()
-    _check(_lib.nao_plan_create(ctypes.byref(d.struct), len(xyz), _p(xyz, _c_dp), int(max_batch), ctypes.byref(h)))
+    _check(_lib.nao_plan_create_ex(ctypes.byref(d.struct), len(xyz), _p(xyz, _c_dp), int(max_batch),
+                                   BATCHERS[batcher], ctypes.byref(h)))
     try:
         nbas, nb, nl = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
         _check(_lib.nao_plan_info(h, ctypes.byref(nbas), ctypes.byref(nb), ctypes.byref(nl)))
@@ -271,19 +279,19 @@ class Context:
                                  RUN_CAPTURE_GRAPH if capture_graph else 0), self.handle)
 
 
-def build_batches(ctx, basis, xyz, w, max_batch):
-    """nao_build_batches: resident device state of one structure."""
-    return System(ctx, basis, xyz, w, max_batch)
+def build_batches(ctx, basis, xyz, w, max_batch, batcher="octree"):
+    """nao_build_batches_ex: resident device state of one structure."""
+    return System(ctx, basis, xyz, w, max_batch, batcher)
 
 
 class System:
-    def __init__(self, ctx, basis, xyz, w, max_batch):
+    def __init__(self, ctx, basis, xyz, w, max_batch, batcher="octree"):
         d = _Desc(basis)
         xyz = _f64(xyz).reshape(-1, 3)
         w = _f64(w)
         h = _vp()
-        _check(_lib.nao_build_batches(ctx.handle, ctypes.byref(d.struct), len(xyz), _p(xyz, _c_dp), _p(w, _c_dp),
-                                      int(max_batch), ctypes.byref(h)), ctx.handle)
+        _check(_lib.nao_build_batches_ex(ctx.handle, ctypes.byref(d.struct), len(xyz), _p(xyz, _c_dp), _p(w, _c_dp),
+                                         int(max_batch), BATCHERS[batcher], ctypes.byref(h)), ctx.handle)
         self.ctx = ctx
         self.handle = h
         ctx._children.add(self)

@@ -106,3 +106,47 @@ def test_plan_empty_and_errors():
     with pytest.raises(nao.NaoError) as e:
         nao.plan_create(w["basis"], xyz, 200)
     assert "non-finite" in str(e.value)
+
+
+def _oracle_cutplane_plan(basis, xyz, max_batch):
+    B = ob.Basis(basis)
+    perm, bp = bt.cutplane_batches(xyz, max_batch)
+    lp, li = bt.basis_lists(xyz, perm, bp, B)
+    return perm, bp, lp, li
+
+
+@pytest.mark.parametrize("cfg,max_batch", [(1, 100), (1, 200), (2, 200), (2, 256)])
+def test_cutplane_plan_bit_exact_configs(cfg, max_batch):
+    from paper_1912_06636_amd import nao
+    w = g.config_workload(cfg, with_density=False)
+    got = nao.plan_create(w["basis"], w["xyz"], max_batch, batcher="cutplane")
+    assert _same(got, _oracle_cutplane_plan(w["basis"], w["xyz"], max_batch))
+    assert len(got[1]) - 1 == -(-len(w["xyz"]) // max_batch)
+
+
+@pytest.mark.parametrize("max_batch", [1, 2, 3, 32, 4096])
+def test_cutplane_bit_exact_sizes_and_degenerate_points(max_batch):
+    from paper_1912_06636_amd import nao
+    xyz = np.array([[0.0, 0.0, 0.0], [1.9, 0.3, -0.4], [0.5, 2.1, 0.7], [3.0, 2.0, 1.0]])
+    basis = g.make_basis(xyz, np.array([0, 1, 0, 1], np.int32), [(0, 1, 2, 3), (0, 0, 1)], [4.5, 3.0], 7, 0)
+    X, _, _ = g.make_grid(xyz, 4.5, 10, 26)
+    assert _same(nao.plan_create(basis, X, max_batch, batcher="cutplane"),
+                 _oracle_cutplane_plan(basis, X, max_batch))
+    same = np.zeros((300, 3)) + 1.25                # coincident points: the index order decides
+    same[150:, 2] = -0.0
+    same[:150, 2] = 0.0
+    assert _same(nao.plan_create(basis, same, max_batch, batcher="cutplane"),
+                 _oracle_cutplane_plan(basis, same, max_batch))
+    with pytest.raises(KeyError):
+        nao.plan_create(basis, X, max_batch, batcher="kdtree")
+
+
+def test_unknown_batcher_is_rejected():
+    from paper_1912_06636_amd import nao
+    w = g.config_workload(1, with_density=False)
+    d = nao._Desc(w["basis"])
+    xyz = np.ascontiguousarray(w["xyz"], dtype=np.float64)
+    h = ctypes.c_void_p()
+    st = nao._lib.nao_plan_create_ex(ctypes.byref(d.struct), len(xyz), xyz.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                     200, 7, ctypes.byref(h))
+    assert st == nao.ERR_INVALID_ARG and not h.value
