@@ -33,9 +33,9 @@ KERNELS_SRC = os.path.join(ROOT, "paper_1912_06636_amd", "csrc", "kernels.hip")
 # --pmc passes (FETCH_SIZE, WRITE_SIZE) over "bench.py --steps 1 --warmup 0 --h-tile 64
 # --no-cpu-baseline --calibrate-copy 1024", each counter scaled by its reading of the 1 GiB
 # plain copy made in that run.  Valid only for the kernel source it was taken on (sha256).
-TRAFFIC = {"sha256": "6b2b17a99d23de21f0c0a8de695842f89b509edeb63651655890eef2ba9de5d5",
+TRAFFIC = {"sha256": "8f6eea4dd6094d4d27aac3c8fb485ef3d6a3fbceefa851d3fab3e979f1d957a8",
            "workload": "slab375", "precision": "fp64", "h_tile": 64, "group_max": 256,
-           "bytes_per_launch": {"n_f64": 5.961e9, "h_f64": 6.019e9}}
+           "bytes_per_launch": {"n_f64": 5.948e9, "h_f64": 6.019e9}}
 WORKLOADS = {
     "slab375": (4, "375-atom layered slab, 28 NAO/atom (10,500 basis functions, l<=3, 6 A cutoff), "
                    "60x434 grid/atom = 9,765,000 points, octree batches <= 256"),
@@ -369,21 +369,37 @@ def main():
             return ms, {k: round(t, 3) for k, (c, t) in prof.items()}
 
         n_mean, h_mean = float(np.mean(n_ms)), float(np.mean(h_ms))
+        peak = PEAK.get(prec, PEAK["fp64"])
+
+        def mfma_rate(kern, name, flops):
+            """Credited TFLOP/s of one contraction kernel and its fraction of the MFMA peak."""
+            t = kern.get(name)
+            if not t:
+                return None
+            tf = flops / (t * 1e-3) / 1e12
+            return {"kernel": name, "achieved": round(tf, 3), "peak": peak, "unit": "TFLOP/s",
+                    "frac": round(tf / peak, 4), "flops": flops}
+
         gn = torch.empty((sysm.n_points, 3), dtype=torch.float64, device=dev)
         g_ms, kern = time_op(lambda: sysm.update_density_gradient(D, precision=prec, out=n, out_grad=gn))
+        # full product Phi D (2|B|m^2) and four row dots (8|B|m)
         grad = {"ms": round(g_ms, 3), "vs_density": round(g_ms / n_mean, 3),
-                "gpt_basis2_per_s": round(U / (g_ms * 1e-3) / 1e9, 3), "kernels_ms": kern}
+                "gpt_basis2_per_s": round(U / (g_ms * 1e-3) / 1e9, 3), "kernels_ms": kern,
+                "mfma": mfma_rate(kern, "ngrad_" + sfx, 2.0 * U + 8.0 * sum_Bm)}
         log("density + gradient: %.2f ms (%.2fx the density alone); kernels: %s" % (g_ms, g_ms / n_mean, kern))
         del gn
         # Hamiltonian with a seeded vector field (the GGA term), and with the kinetic term
         a = torch.from_numpy(0.3 * np.random.default_rng(99).normal(size=(sysm.n_points, 3))).to(dev)
         ms, kern = time_op(lambda: sysm.integrate_h_gga(v, a, precision=prec, out=H))
+        # two products per upper-triangle tile pair: 2 |B| m (m+1)
         grad["hamiltonian_with_field"] = {"ms": round(ms, 3), "vs_hamiltonian": round(ms / h_mean, 3),
-                                          "kernels_ms": kern}
+                                          "kernels_ms": kern,
+                                          "mfma": mfma_rate(kern, "hgga_" + sfx, 2.0 * U + 2.0 * sum_Bm)}
         log("hamiltonian with a vector field: %.2f ms (%.2fx the local one); kernels: %s" % (ms, ms / h_mean, kern))
         ms, kern = time_op(lambda: sysm.integrate_h_ks(v, precision=prec, out=H))
         grad["hamiltonian_kinetic"] = {"ms": round(ms, 3), "vs_hamiltonian": round(ms / h_mean, 3),
-                                       "kernels_ms": kern}
+                                       "kernels_ms": kern,
+                                       "mfma": mfma_rate(kern, "hks_" + sfx, 2.0 * U + 2.0 * sum_Bm)}
         log("hamiltonian with the kinetic term: %.2f ms (%.2fx the local one); kernels: %s" % (ms, ms / h_mean, kern))
         del a
         # local Pulay forces with a seeded energy-weighted density matrix
@@ -391,7 +407,9 @@ def main():
         Q = torch.from_numpy(energy_weighted_for(work, 1)).to(dev)
         F = torch.empty((sysm.n_atoms, 3), dtype=torch.float64, device=dev)
         ms, kern = time_op(lambda: sysm.pulay_forces(D, Q, v, precision=prec, out=F))
-        grad["pulay_forces"] = {"ms": round(ms, 3), "vs_density": round(ms / n_mean, 3), "kernels_ms": kern}
+        # two full products (4|B|m^2), row weights (2|B|m) and three column dots (6|B|m)
+        grad["pulay_forces"] = {"ms": round(ms, 3), "vs_density": round(ms / n_mean, 3), "kernels_ms": kern,
+                                "mfma": mfma_rate(kern, "nforce_" + sfx, 4.0 * U + 8.0 * sum_Bm)}
         log("local Pulay forces: %.2f ms (%.2fx the density alone); kernels: %s" % (ms, ms / n_mean, kern))
         del Q, F
 
