@@ -140,9 +140,11 @@ constexpr size_t BASIS_LDS_BYTES = (size_t)MAX_SPLINE_LDS * sizeof(double);
 
 constexpr int BASIS_ATOMS = 256;   // atoms of a unit staged in LDS
 constexpr int BASIS_SHELLS = 128;  // shells of a system staged in LDS
+constexpr int BASIS_SLICES = 4;    // work items per unit (point slices) of the basis kernel
 
-// Basis values of execution units: one workgroup per unit; threads over (point, atom) pairs
-// with the atom fastest, each writing all functions of its atom.  The unit's atoms (position,
+// Basis values of execution units: BASIS_SLICES workgroups per unit, each taking a contiguous
+// slice of the unit's points (more workgroups in flight than one per unit, and shorter tails);
+// threads over (point, atom) pairs with the atom fastest, each writing all functions of its atom.  The unit's atoms (position,
 // cutoff, species, first column) and the system's shell tables (l, radial function and its
 // parameters) are staged in LDS first, so that a pair's chain of table lookups stays on chip;
 // a unit or system larger than the staging arrays reads them from global memory instead.
@@ -159,12 +161,18 @@ __global__ __launch_bounds__(256) void basis_kernel(const DevSeg* __restrict__ s
     (void)spline_lds;  // the launcher sized the dynamic LDS for the table
     const int tid = threadIdx.x;
     for (int64_t v_ = blockIdx.x; v_ < xcd_span(total); v_ += gridDim.x) {
-        const int64_t b = xcd_item(v_, total);
-        if (b >= total) continue;
+        const int64_t bi = xcd_item(v_, total);
+        if (bi >= total) continue;
+        // item = (unit, slice): BASIS_SLICES consecutive items split one unit's points
+        const int64_t b = bi / BASIS_SLICES;
+        const int slice = (int)(bi - b * BASIS_SLICES);
         __syncthreads();  // the previous item may still read LDS
         const int s = find_segment(segs, n_segs, b, [](const DevSeg& g) { return g.unit_prefix; });
         const DevSeg& sg = segs[s];
         const DevUnit u = sg.units[sg.unit_begin + (b - sg.unit_prefix)];
+        const int row0 = (int)(((int64_t)u.n_points * slice) / BASIS_SLICES);
+        const int row1 = (int)(((int64_t)u.n_points * (slice + 1)) / BASIS_SLICES);
+        if (row1 <= row0) continue;
         const DevSys* S = sg.sys;
         const int nk = S->n_knots;
         const int na = u.n_atoms, n_sp = S->n_species, n_sh = S->n_shells;
@@ -208,14 +216,16 @@ __global__ __launch_bounds__(256) void basis_kernel(const DevSeg* __restrict__ s
         const bool field = GGA || (KS && sg.wa != nullptr);  // uniform
         constexpr int XW = GRAD ? 3 : 1;  // extra values per basis value
         gp<T> __restrict__ gout = EX != EXTRA_NONE ? gptr(static_cast<T*>(sg.gphi) + XW * u.out_offset) : nullptr;
-        const int64_t npairs = (int64_t)u.n_points * na;
+        const int64_t npairs = (int64_t)(row1 - row0) * na;
         const double tmax = (double)(nk - 1);
 
         auto pairs = [&](auto on_chip) {
             constexpr bool ST = decltype(on_chip)::value;
             for (int64_t q = tid; q < npairs; q += blockDim.x) {
-                const int pl = (int)(q / na);
-                const int ai = (int)(q - (int64_t)pl * na);
+                const int ql = (int)q;
+                const int pq = ql / na;
+                const int ai = ql - pq * na;
+                const int pl = row0 + pq;
                 const int atom = ST ? 0 : uat[ai];
                 int col = ST ? s_aspc[ai][1] : ucol[ai];
                 const int64_t p = u.point_begin + pl;
@@ -352,12 +362,13 @@ __global__ __launch_bounds__(256) void basis_kernel(const DevSeg* __restrict__ s
         else pairs(std::false_type{});
         const int pad = u.ld - u.m;
         if (pad > 0) {
-            const int64_t ne = (int64_t)u.n_points * pad;
+            const int64_t ne = (int64_t)(row1 - row0) * pad;
             for (int64_t q = tid; q < ne; q += blockDim.x) {
-                const int64_t pl = q / pad;
-                out[pl * u.ld + u.m + (q - pl * pad)] = T(0);
+                const int64_t pl = row0 + q / pad;
+                const int64_t cpad = q - (pl - row0) * pad;
+                out[pl * u.ld + u.m + cpad] = T(0);
                 if (EX != EXTRA_NONE)
-                    for (int c = 0; c < XW; ++c) gout[XW * (pl * u.ld + u.m + (q - pl * pad)) + c] = T(0);
+                    for (int c = 0; c < XW; ++c) gout[XW * (pl * u.ld + u.m + cpad) + c] = T(0);
             }
         }
     }
@@ -377,10 +388,11 @@ hipError_t launch_basis(const DevSeg* segs_dev, int n_segs, int64_t n_units, int
                         hipStream_t st, int64_t max_grid, int extra)
 {
     if (n_units <= 0 || n_segs <= 0) return hipSuccess;
-    if (n_units > 0x7ffffff0 || spline_lds < 0 || spline_lds > MAX_SPLINE_LDS) return hipErrorInvalidValue;
+    if (n_units > 0x7ffffff0 / BASIS_SLICES || spline_lds < 0 || spline_lds > MAX_SPLINE_LDS) return hipErrorInvalidValue;
     if (extra != EXTRA_NONE && extra != EXTRA_GRAD && extra != EXTRA_GGA_L && extra != EXTRA_KS_L)
         return hipErrorInvalidValue;
-    const dim3 g(grid_for(n_units, max_grid)), b(256);
+    const int64_t n_items = n_units * BASIS_SLICES;
+    const dim3 g(grid_for(n_items, max_grid)), b(256);
     const bool staged = spline_lds > 0;
     const size_t lds = (size_t)spline_lds * sizeof(double);
     // dynamic LDS above 64 KiB must be allowed per kernel, once per device
@@ -408,8 +420,8 @@ hipError_t launch_basis(const DevSeg* segs_dev, int n_segs, int64_t n_units, int
     }
 #define NAO_BASIS_LAUNCH(TT, EE)                                                                                 \
     do {                                                                                                       \
-        if (staged) hipLaunchKernelGGL((basis_kernel<TT, true, EE>), g, b, lds, st, segs_dev, n_segs, n_units, spline_lds); \
-        else hipLaunchKernelGGL((basis_kernel<TT, false, EE>), g, b, lds, st, segs_dev, n_segs, n_units, 0);  \
+        if (staged) hipLaunchKernelGGL((basis_kernel<TT, true, EE>), g, b, lds, st, segs_dev, n_segs, n_items, spline_lds); \
+        else hipLaunchKernelGGL((basis_kernel<TT, false, EE>), g, b, lds, st, segs_dev, n_segs, n_items, 0);  \
     } while (0)
 #define NAO_BASIS_EXTRA(TT)                                           \
     do {                                                              \
@@ -438,6 +450,24 @@ hipError_t launch_basis(const DevSeg* segs_dev, int n_segs, int64_t n_units, int
 // (v_mfma_f32_16x16x4f32).  Operand layouts of both: A lane l holds A[l%16][l/16], B lane l
 // holds B[l/16][l%16].  The result register r of lane l is D[l/16 + 4r][l%16] for FP64 and
 // D[4(l/16) + r][l%16] for FP32 (measured on gfx950).
+
+// Sum over the 16 lanes of each DPP row (lanes 16 r .. 16 r + 15), every lane receiving the sum:
+// quad swaps (xor 1, xor 2), then the half-row and row mirrors pair the quads.
+template <int CTRL>
+__device__ inline double dpp_move(double x)
+{
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ inline double row_sum16(double v)
+{
+    v += dpp_move<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+    v += dpp_move<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+    v += dpp_move<0x141>(v);  // row_half_mirror
+    v += dpp_move<0x140>(v);  // row_mirror
+    return v;
+}
 
 template <typename T> struct Mma;
 template <> struct Mma<double> {
@@ -1003,11 +1033,7 @@ __global__ __launch_bounds__(64 * NW) void n_kernel(const DevSeg* __restrict__ s
                         for (int qq = 0; qq < NQ; ++qq) {
                             const double f = qq == 0 ? (double)phi[e]
                                                      : (double)gptr(static_cast<const T*>(sg.gphi) + 3 * u.out_offset)[3 * e + qq - 1];
-                            double v = live ? (double)acc[q][r] * f : 0.0;
-                            v += __shfl_xor(v, 1);
-                            v += __shfl_xor(v, 2);
-                            v += __shfl_xor(v, 4);
-                            v += __shfl_xor(v, 8);
+                            const double v = row_sum16(live ? (double)acc[q][r] * f : 0.0);
                             if (lr == 0) red[qq][cb][p] = v;
                         }
                     }
@@ -1362,11 +1388,7 @@ __global__ __launch_bounds__(1024) void n_kernel_bf16(const DevSeg* __restrict__
                     for (int r = 0; r < 4; ++r) {
                         const int p = pblk * 16 + lk * 4 + r;
                         const double f = (double)phi[(int64_t)min(p, np - 1) * ld + cj];
-                        double v = (p < np && cj < m) ? acc64[q][r] * f : 0.0;
-                        v += __shfl_xor(v, 1);
-                        v += __shfl_xor(v, 2);
-                        v += __shfl_xor(v, 4);
-                        v += __shfl_xor(v, 8);
+                        const double v = row_sum16((p < np && cj < m) ? acc64[q][r] * f : 0.0);
                         if (lr == 0) red[cb][p] = v;
                     }
                 }
