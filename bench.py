@@ -33,9 +33,9 @@ KERNELS_SRC = os.path.join(ROOT, "paper_1912_06636_amd", "csrc", "kernels.hip")
 # --pmc passes (FETCH_SIZE, WRITE_SIZE) over "bench.py --steps 1 --warmup 0 --h-tile 64
 # --no-cpu-baseline --calibrate-copy 1024", each counter scaled by its reading of the 1 GiB
 # plain copy made in that run.  Valid only for the kernel source it was taken on (sha256).
-TRAFFIC = {"sha256": "8f6eea4dd6094d4d27aac3c8fb485ef3d6a3fbceefa851d3fab3e979f1d957a8",
+TRAFFIC = {"sha256": "ba48d87d51e18420a08cd674b218d00ea9581cf7a2b4b82655a29916c0441214",
            "workload": "slab375", "precision": "fp64", "h_tile": 64, "group_max": 256,
-           "bytes_per_launch": {"n_f64": 5.948e9, "h_f64": 6.019e9}}
+           "bytes_per_launch": {"n_f64": 5.910e9, "h_f64": 6.019e9}}
 WORKLOADS = {
     "slab375": (4, "375-atom layered slab, 28 NAO/atom (10,500 basis functions, l<=3, 6 A cutoff), "
                    "60x434 grid/atom = 9,765,000 points, octree batches <= 256"),
