@@ -1,4 +1,4 @@
-"""Full-size cut-plane batches (kept out of collection until it has passed on the GPU)."""
+"""Full-size cut-plane batches: results against the octree path and, on the block, batches and lists against the oracle."""
 import numpy as np
 import pytest
 
