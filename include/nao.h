@@ -182,6 +182,18 @@ nao_status nao_build_batches_ex(nao_ctx ctx, const nao_basis_desc* basis, int64_
  * every batch as its own unit (no packing).  Results change only by floating-point
  * summation order. */
 nao_status nao_system_set_group_max(nao_system sys, int32_t group_max);
+/* Keep the basis values of every block resident in device memory across operations
+ * (enable = 1): nao_integrate_h and nao_update_density then evaluate them once per value type
+ * (FP64, or FP32 for the reduced-precision modes) and reuse them until the execution groups
+ * change (nao_system_set_group_max, nao_system_set_h_tile, nao_system_autotune), the geometry
+ * of a system being fixed (the SCF case: the same points and basis at every iteration).
+ * Costs 8 bytes per basis value of the whole system (the sum of its blocks), charged to the
+ * context's HBM budget: NAO_ERR_BUDGET (or NAO_ERR_OUT_OF_MEMORY from the device) leaves the
+ * mode off, and so does a later change of groups whose layout no longer fits (that call then
+ * returns the same status).
+ * Results equal those of the default mode up to the order of the FP64 atomic accumulation.  The other operations (gradients, fields,
+ * forces, nao_run_many, nao_eval_basis) evaluate as before.  enable = 0 frees the memory. */
+nao_status nao_system_set_resident_basis(nao_system sys, int enable);
 /* Tile width (64 or 128 basis functions) of the Hamiltonian kernel for this system; wider
  * tiles stage each basis value for twice the MFMA work, narrower ones waste less padding.
  * Results change only by floating-point summation order.  The reduced-precision split-BF16

@@ -283,6 +283,11 @@ struct nao_system_s {
         d_radial_par, d_spline, d_fn_ptr, d_fn_code;
     DevArray d_units, d_unit_atoms, d_unit_cols, d_unit_fn, d_h_items, d_hw_items, d_n_items;
     DevArray d_wv, d_v, d_D, d_H, d_n, d_gn, d_a, d_wa, d_segs, d_Q, d_fb, d_atom_first, d_F;
+    // resident basis values (opt-in): every block's values kept across operations
+    bool resident = false;
+    int res_kind = -1;              // -1: not evaluated, 0: FP64 values, 1: FP32 values
+    std::vector<int64_t> res_off;   // element offset of every block
+    DevArray d_phi_res;
     int spline_lds = 0;  // doubles of spline table staged in LDS by the basis kernel (0 = not staged)
 };
 
@@ -295,7 +300,7 @@ size_t system_bytes(const nao_system_s* s)
                              &s->d_spline, &s->d_fn_ptr, &s->d_fn_code, &s->d_units, &s->d_unit_atoms, &s->d_unit_cols, &s->d_unit_fn,
                              &s->d_h_items, &s->d_hw_items, &s->d_n_items, &s->d_wv, &s->d_v, &s->d_D, &s->d_H, &s->d_n,
                              &s->d_gn, &s->d_a, &s->d_wa, &s->d_segs, &s->d_Q, &s->d_fb, &s->d_atom_first,
-                             &s->d_F};
+                             &s->d_F, &s->d_phi_res};
     size_t t = 0;
     for (auto* a : arr) t += a->bytes;
     return t;
@@ -307,7 +312,7 @@ void free_all(nao_system_s* s)
                        &s->d_species, &s->d_shell_ptr, &s->d_shell_l, &s->d_shell_rad, &s->d_radial_par,
                        &s->d_spline, &s->d_fn_ptr, &s->d_fn_code, &s->d_units, &s->d_unit_atoms, &s->d_unit_cols, &s->d_unit_fn,
                        &s->d_h_items, &s->d_hw_items, &s->d_n_items, &s->d_wv, &s->d_v, &s->d_D, &s->d_H, &s->d_n, &s->d_gn, &s->d_a, &s->d_wa, &s->d_segs,
-                       &s->d_Q, &s->d_fb, &s->d_atom_first, &s->d_F};
+                       &s->d_Q, &s->d_fb, &s->d_atom_first, &s->d_F, &s->d_phi_res};
     for (auto* a : arr) {
         dev_free(s->ctx, a->p, a->bytes);
         a->p = nullptr;
@@ -316,6 +321,30 @@ void free_all(nao_system_s* s)
 }
 
 int32_t round_up(int32_t x, int32_t m) { return (x + m - 1) / m * m; }
+
+// Resident basis values: one slot per block (8 bytes per value, FP32 modes use half), marked
+// not evaluated.  When the new layout does not fit the budget the mode turns off and the status
+// is returned.
+nao_status resident_layout(nao_system_s* s)
+{
+    s->res_kind = -1;
+    if (!s->resident) return NAO_OK;
+    s->res_off.clear();
+    int64_t total = 0;
+    for (const Block& b : s->blocks) {
+        s->res_off.push_back(total);
+        total += b.phi_elems;
+    }
+    const nao_status st = ensure(s->ctx, s->d_phi_res, (size_t)std::max<int64_t>(1, total) * sizeof(double));
+    if (st != NAO_OK) {
+        dev_free(s->ctx, s->d_phi_res.p, s->d_phi_res.bytes);
+        s->d_phi_res.p = nullptr;
+        s->d_phi_res.bytes = 0;
+        s->resident = false;
+        s->res_off.clear();
+    }
+    return st;
+}
 
 // Build execution groups, split them into scratch-sized blocks and upload units and items.
 nao_status build_groups(nao_system_s* s)
@@ -401,7 +430,7 @@ nao_status build_groups(nao_system_s* s)
         c->scratch_elems = need;
     }
     HIP_TRY(c, hipStreamSynchronize(c->stream));
-    return NAO_OK;
+    return resident_layout(s);
 }
 
 // Hamiltonian segments use the 128-wide items when wide is set (FP64 / FP32 on systems with
@@ -1171,6 +1200,27 @@ nao_status nao_system_set_group_max(nao_system s, int32_t group_max)
     }
 }
 
+nao_status nao_system_set_resident_basis(nao_system s, int enable)
+{
+    if (!s) return (g_thread_error = "system is NULL", NAO_ERR_INVALID_ARG);
+    nao_status st = check_ctx(s->ctx);
+    if (st != NAO_OK) return st;
+    if (enable != 0 && enable != 1) return (set_err(s->ctx, "enable must be 0 or 1"), NAO_ERR_INVALID_ARG);
+    HIP_TRY(s->ctx, hipStreamSynchronize(s->ctx->stream));
+    if (!enable) {
+        dev_free(s->ctx, s->d_phi_res.p, s->d_phi_res.bytes);
+        s->d_phi_res.p = nullptr;
+        s->d_phi_res.bytes = 0;
+        s->resident = false;
+        s->res_kind = -1;
+        s->res_off.clear();
+        return NAO_OK;
+    }
+    s->resident = true;
+    st = resident_layout(s);
+    return st;  // the allocation's own message says what did not fit
+}
+
 nao_status nao_system_set_h_tile(nao_system s, int32_t h_tile)
 {
     if (!s) return (g_thread_error = "system is NULL", NAO_ERR_INVALID_ARG);
@@ -1331,8 +1381,13 @@ static nao_status run_blocks(nao_system s, bool ham, nao_precision prec, const d
     nao_ctx c = s->ctx;
     std::vector<DevSeg> segs;
     const bool wide = ham && s->h_tile == 128 && (prec == NAO_FP64 || prec == NAO_FP32);
-    for (const Block& b : s->blocks) {
-        DevSeg g = make_seg(s, b, ham, wide);
+    // resident mode: each block reads its own slot, evaluated once per value type
+    const bool res = s->resident && s->d_phi_res.p && s->res_off.size() == s->blocks.size();
+    const int kind = f32 ? 1 : 0;
+    const bool evaluate = !res || s->res_kind != kind;
+    for (size_t k = 0; k < s->blocks.size(); ++k) {
+        DevSeg g = make_seg(s, s->blocks[k], ham, wide);
+        if (res) g.phi = static_cast<char*>(s->d_phi_res.p) + s->res_off[k] * (f32 ? sizeof(float) : sizeof(double));
         g.wv = wv;
         g.D = D;
         g.H = H;
@@ -1343,8 +1398,9 @@ static nao_status run_blocks(nao_system s, bool ham, nao_precision prec, const d
     HIP_TRY(c, hipMemcpyAsync(s->d_segs.p, segs.data(), segs.size() * sizeof(DevSeg), hipMemcpyHostToDevice,
                               c->stream));
     DevSeg* dseg = s->d_segs.as<DevSeg>();
+    if (res && evaluate) s->res_kind = -1;  // marked valid only once every block is enqueued
     for (size_t k = 0; k < segs.size(); ++k) {
-        if (staged)
+        if (staged && evaluate)
             LAUNCH(c, f32 ? "basis_f32" : "basis_f64",
                    launch_basis(dseg + k, 1, segs[k].unit_count, s->spline_lds, f32, c->stream));
         if (ham)
@@ -1353,6 +1409,7 @@ static nao_status run_blocks(nao_system s, bool ham, nao_precision prec, const d
         else
             LAUNCH(c, kname(false, prec), launch_n(mode, dseg + k, 1, segs[k].item_count, c->stream));
     }
+    if (res) s->res_kind = kind;
     return NAO_OK;
 }
 

@@ -79,6 +79,7 @@ _sig("nao_build_batches", _S, _vp, ctypes.POINTER(BasisDesc), ctypes.c_int64, _c
 _sig("nao_build_batches_ex", _S, _vp, ctypes.POINTER(BasisDesc), ctypes.c_int64, _c_dp, _c_dp, ctypes.c_int32,
      ctypes.c_int, ctypes.POINTER(_vp))
 _sig("nao_system_set_group_max", _S, _vp, ctypes.c_int32)
+_sig("nao_system_set_resident_basis", _S, _vp, ctypes.c_int)
 _sig("nao_system_set_h_tile", _S, _vp, ctypes.c_int32)
 _sig("nao_system_autotune", _S, _vp, ctypes.c_int, _vp, _vp, ctypes.c_int, ctypes.c_uint32, _c_i32p, _c_i32p, _c_dp)
 _sig("nao_system_info", _S, _vp, _c_i64p, _c_i64p, _c_i64p, ctypes.POINTER(ctypes.c_size_t))
@@ -111,6 +112,7 @@ EXPORTED = [
     "nao_plan_destroy", "nao_build_batches", "nao_system_set_group_max", "nao_system_set_h_tile", "nao_system_autotune", "nao_system_info", "nao_get_batches",
     "nao_system_work", "nao_eval_basis", "nao_integrate_h", "nao_update_density", "nao_update_density_gradient", "nao_integrate_h_gga",
     "nao_pulay_forces", "nao_integrate_h_ks", "nao_plan_create_ex", "nao_build_batches_ex",
+    "nao_system_set_resident_basis",
     "nao_system_destroy",
     "nao_run_many", "nao_server_create", "nao_server_open_session", "nao_server_close_session",
     "nao_server_session_info", "nao_server_submit", "nao_server_step", "nao_server_poll", "nao_server_result",
@@ -320,6 +322,10 @@ class System:
 
     def set_group_max(self, g):
         _check(_lib.nao_system_set_group_max(self.handle, int(g)), self.ctx.handle)
+
+    def set_resident_basis(self, enable=True):
+        """nao_system_set_resident_basis: keep the basis values resident across operations."""
+        _check(_lib.nao_system_set_resident_basis(self.handle, 1 if enable else 0), self.ctx.handle)
 
     def set_h_tile(self, t):
         _check(_lib.nao_system_set_h_tile(self.handle, int(t)), self.ctx.handle)
