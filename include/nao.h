@@ -1,7 +1,10 @@
 /*
  * nao.h -- C ABI of the MI355X (gfx950) real-space grid engine for numeric
  * atom-centred orbitals: batch-wise Hamiltonian integration and density
- * update over spatially compact batches of integration points.
+ * update over spatially compact batches of integration points, with the
+ * operations built on the same batches: the density gradient, the Hamiltonian
+ * with a GGA-type vector field or with the kinetic term, and the local Pulay
+ * forces; batches by octree or by the paper's cut-plane partition.
  *
  * Method: Huhn, Lange, Yu, Yoon, Blum, "GPGPU Acceleration of All-Electron
  * Electronic Structure Theory Using Localized Numeric Atom-Centered Basis
