@@ -53,3 +53,14 @@ def test_invariants_on_a_workload(mb):
     assert len(sizes) == -(-len(xyz) // mb)  # quantile cuts give exactly ceil(n / mb) batches
     for b in batches(perm, bp):
         assert b == sorted(b)
+
+
+def test_planted_midpoint_cut_fails_the_worked_example():
+    """Cutting at the geometric midpoint instead of the point quantile changes the batches of
+    the worked example (points clustered towards one end)."""
+    xs = np.array([0.0, 0.1, 0.2, 0.3, 0.4, 9.0])
+    xyz = np.stack([xs, np.zeros(6), np.zeros(6)], axis=1)
+    perm, bp = ob.cutplane_batches(xyz, 3)
+    assert batches(perm, bp) == [[0, 1, 2], [3, 4, 5]]
+    mid = 0.5 * (xs.min() + xs.max())
+    assert [list(np.nonzero(xs < mid)[0]), list(np.nonzero(xs >= mid)[0])] != batches(perm, bp)

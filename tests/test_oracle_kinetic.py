@@ -122,3 +122,21 @@ def test_ks_entries_equal_full_matrix():
         H = oi.hamiltonian_ks(B, X, w, v, field)
         got = oi.hamiltonian_ks_entries(B, X, w, v, field, pairs)
         assert np.max(np.abs(got - np.array([H[i, j] for i, j in pairs]))) <= 1e-12 * np.max(np.abs(H))
+
+
+def test_planted_dropped_angular_term_fails(monkeypatch):
+    """A Laplacian without the -l(l+1) R / r^2 term must fail the finite-difference pin."""
+    B = ob.Basis(two_species())
+    pts = sample_points(B, 30, 7)
+    real = osp.radial_laplacian
+
+    def wrong(r, y, M, rmin, rcut, l):
+        return real(r, y, M, rmin, rcut, 0)  # planted: angular term dropped
+
+    monkeypatch.setattr(osp, "radial_laplacian", wrong)
+    lap = B.lap_phi_atom(pts, 0)
+    fd = -6.0 * B.phi_atom(pts, 0)
+    for e in np.eye(3) * STEP:
+        fd = fd + B.phi_atom(pts + e, 0) + B.phi_atom(pts - e, 0)
+    fd = fd / (STEP * STEP)
+    assert np.max(np.abs(lap - fd)) > 1e-3 * np.max(np.abs(fd))
