@@ -33,7 +33,7 @@ KERNELS_SRC = os.path.join(ROOT, "paper_1912_06636_amd", "csrc", "kernels.hip")
 # --pmc passes (FETCH_SIZE, WRITE_SIZE) over "bench.py --steps 1 --warmup 0 --h-tile 64
 # --no-cpu-baseline --calibrate-copy 1024", each counter scaled by its reading of the 1 GiB
 # plain copy made in that run.  Valid only for the kernel source it was taken on (sha256).
-TRAFFIC = {"sha256": "a7ed0cb2d3a10340ec32cdb10aed89a74cdeb99750d390844db7f547e1577279",
+TRAFFIC = {"sha256": "fde1e6b66bb516aef319c6624617b7236cb5804fa77c4899712fe37f9fe52f48",
            "workload": "slab375", "precision": "fp64", "h_tile": 64, "group_max": 256,
            "bytes_per_launch": {"n_f64": 5.910e9, "h_f64": 6.019e9}}
 WORKLOADS = {
