@@ -251,7 +251,8 @@ nao_status nao_integrate_h(nao_system sys, const double* v, nao_memspace v_space
  * batch through the batch density matrix D[nnz(B), nnz(B)] (Section "GPGPU Acceleration
  * of the Real-Space Domain Decomposition Algorithm").  D [N_b][N_b] row-major is symmetric;
  * like the symmetric matrix product used for it in the paper, only its upper triangle
- * (i <= j) is read.
+ * (i <= j) is read: for a D that is not symmetric the result is that of the symmetric matrix
+ * with D's upper triangle, D_ji := D_ij for i < j (not that of (D + D^T) / 2).
  * n [n_points] in caller point order (exact zeros where no basis function reaches).
  * n_electrons (host, nullable) receives N_e = sum_p w_p n_p; passing it synchronizes.
  * ------------------------------------------------------------------------------------- */
@@ -326,25 +327,33 @@ void nao_system_destroy(nao_system sys);
 /* ---------------------------------------------------------------------------------------
  * Many structures in one launch sequence: the work of every entry (op 0 = H with in = v,
  * out = H; op 1 = density with in = D, out = n) is packed into one work list per kernel
- * and launched together.  All pointers are device memory of the context's device; every
- * system must belong to ctx.  NAO_RUN_CAPTURE_GRAPH records the sequence into a HIP graph
- * on first use and replays it while the (systems, pointers, precision) tuple repeats.
- * n_electrons must be NULL here (use nao_update_density for it).
+ * and launched together (eq. H_decomp: the batches of all structures are independent units
+ * of work).  in and out are device memory of the context's device; every system must belong
+ * to ctx.  n_electrons (op 1 only; host memory, nullable) receives N_e = sum_p w_p n_p of that
+ * entry, and the call then synchronizes.
+ * hip_stream: NULL runs the work on the context's stream; otherwise it runs on that stream of
+ * the context's device, after the work already enqueued on the context's stream, and the
+ * context's stream waits for it before its next work (the context's scratch is shared).
+ * NAO_RUN_CAPTURE_GRAPH records the sequence into a HIP graph on first use and replays it
+ * while the (systems, pointers, precision) tuple repeats (not with n_electrons: invalid
+ * argument); a graph is dropped when a system it names changes its groups or is destroyed,
+ * and when the context's basis scratch is replaced by a larger one.
  * ------------------------------------------------------------------------------------- */
 typedef struct {
     nao_system sys;
-    int32_t op;         /* 0 = Hamiltonian, 1 = density */
-    const double* in;   /* v [n_points] or D [N_b][N_b] */
-    double* out;        /* H [N_b][N_b] or n [n_points] */
+    int32_t op;            /* 0 = Hamiltonian, 1 = density */
+    const double* in;      /* v [n_points] or D [N_b][N_b] */
+    double* out;           /* H [N_b][N_b] or n [n_points] */
+    double* n_electrons;   /* op 1: host, nullable; op 0: must be NULL */
 } nao_work;
 
 #define NAO_RUN_CAPTURE_GRAPH 1u
 
 nao_status nao_run_many(nao_ctx ctx, const nao_work* work, int64_t n_work, nao_precision precision,
-                        uint32_t flags);
+                        void* hip_stream, uint32_t flags);
 /* Without NAO_RUN_CAPTURE_GRAPH, systems may also belong to another context on the same device
- * (the work then runs on ctx's stream with ctx's scratch); such a system must not be destroyed
- * while that work runs. */
+ * (the work then runs with ctx's scratch); such a system must not be destroyed while that work
+ * runs. */
 
 /* ---------------------------------------------------------------------------------------
  * Serving core: continuous batching of SCF-iteration requests over resident structures.
@@ -396,11 +405,18 @@ nao_status nao_server_session_info(nao_server srv, int64_t session, int32_t* sta
                                    int64_t* n_basis, int64_t* n_points);
 nao_status nao_server_submit(nao_server srv, int64_t session, const double* D, nao_memspace D_space,
                              const double* v, nao_memspace v_space, uint64_t* ticket);
+/* A launch that cannot be enqueued or that reports a failure on completion fails its requests
+ * (NAO_REQ_FAILED) and returns that status; their sessions stay usable.  A request without v
+ * whose session has no potential on the device (its only earlier v came with a request that
+ * failed) fails at launch with NAO_ERR_INVALID_ARG. */
 nao_status nao_server_step(nao_server srv, int32_t* n_running, int32_t* n_waiting);
 nao_status nao_server_poll(nao_server srv, uint64_t ticket, int32_t* state, double* t_submit, double* t_start,
                            double* t_end);
 /* Copy a done request's H [N_b][N_b] and/or n [n_points] (caller order) out; either may be NULL.
- * Valid until the session's next request starts. */
+ * A session keeps one H and n: the result is available until the session's next request
+ * starts, after which this call returns NAO_ERR_INVALID_ARG (read a result before submitting
+ * the next iteration when every iteration's result is needed).  NAO_ERR_NOT_READY while the
+ * request is waiting or running, or when it failed. */
 nao_status nao_server_result(nao_server srv, uint64_t ticket, double* H, double* n, nao_memspace space);
 void nao_server_destroy(nao_server srv);
 

@@ -39,7 +39,7 @@ def build(verbose: bool = False) -> str:
     os.makedirs(OBJ, exist_ok=True)
     inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC, "-I", os.path.join(ROCM, "include")]
     objs = []
-    for src in ("plan.cpp", "runtime.cpp", "server.cpp"):
+    for src in ("plan.cpp", "runtime.cpp", "scheduler.cpp", "server.cpp"):
         o = os.path.join(OBJ, src + ".o")
         _run(["g++"] + CXX_FLAGS + inc + ["-c", os.path.join(CSRC, src), "-o", o], verbose)
         objs.append(o)

@@ -291,6 +291,8 @@ struct nao_system_s {
     int spline_lds = 0;  // doubles of spline table staged in LDS by the basis kernel (0 = not staged)
 };
 
+nao_status grow_scratch(nao_ctx c, size_t elems);
+
 namespace {
 
 size_t system_bytes(const nao_system_s* s)
@@ -420,15 +422,7 @@ nao_status build_groups(nao_system_s* s)
     if ((st = ensure(c, s->d_segs, std::max<size_t>(1, s->blocks.size()) * sizeof(DevSeg))) != NAO_OK) return st;
     size_t need = 0;
     for (const Block& b : s->blocks) need = std::max(need, (size_t)b.phi_elems);
-    if (need > c->scratch_elems) {
-        dev_free(c, c->scratch, c->scratch_elems * sizeof(double));
-        c->scratch = nullptr;
-        c->scratch_elems = 0;
-        void* p = nullptr;
-        if ((st = dev_alloc(c, need * sizeof(double), &p)) != NAO_OK) return st;
-        c->scratch = static_cast<double*>(p);
-        c->scratch_elems = need;
-    }
+    if ((st = grow_scratch(c, need)) != NAO_OK) return st;
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     return resident_layout(s);
 }
@@ -536,6 +530,27 @@ void many_forget(nao_ctx c, const nao_system_s* sys)
     c->many.swap(keep);
 }
 
+}  // namespace
+
+// Replace the context's basis scratch by one of at least `elems` values.  Captured launch plans
+// hold the old buffer's address, so they are dropped first (after the work in flight is done).
+nao_status grow_scratch(nao_ctx c, size_t elems)
+{
+    if (elems <= c->scratch_elems) return NAO_OK;
+    many_forget(c, nullptr);
+    dev_free(c, c->scratch, c->scratch_elems * sizeof(double));
+    c->scratch = nullptr;
+    c->scratch_elems = 0;
+    void* p = nullptr;
+    const nao_status st = dev_alloc(c, elems * sizeof(double), &p);
+    if (st != NAO_OK) return st;
+    c->scratch = static_cast<double*>(p);
+    c->scratch_elems = elems;
+    return NAO_OK;
+}
+
+namespace {
+
 nao_status many_build(nao_ctx c, const nao_work* work, int64_t n_work, nao_precision prec, ManyPlan* m)
 {
     m->prec = prec;
@@ -552,17 +567,7 @@ nao_status many_build(nao_ctx c, const nao_work* work, int64_t n_work, nao_preci
     int64_t need = 0;
     for (const nao_work& w : m->entries)
         for (const Block& b : w.sys->blocks) need = std::max(need, b.phi_elems);
-    if (need > (int64_t)c->scratch_elems) {
-        HIP_TRY(c, hipStreamSynchronize(c->stream));
-        many_retire(c, true);
-        dev_free(c, c->scratch, c->scratch_elems * sizeof(double));
-        c->scratch = nullptr;
-        c->scratch_elems = 0;
-        void* p = nullptr;
-        if ((st = dev_alloc(c, (size_t)need * sizeof(double), &p)) != NAO_OK) return st;
-        c->scratch = static_cast<double*>(p);
-        c->scratch_elems = (size_t)need;
-    }
+    if ((st = grow_scratch(c, (size_t)need)) != NAO_OK) return st;
     // one segment per (entry, block); consecutive segments share a chunk while their basis
     // values fit the scratch
     struct Pending { DevSeg g; bool ham; int64_t phi; int32_t h_tile; };
@@ -1724,30 +1729,70 @@ nao_status nao_pulay_forces(nao_system s, const double* D, const double* Q, cons
     return NAO_OK;
 }
 
-nao_status nao_run_many(nao_ctx c, const nao_work* work, int64_t n_work, nao_precision prec, uint32_t flags)
+nao_status nao_run_many(nao_ctx c, const nao_work* work, int64_t n_work, nao_precision prec, void* hip_stream,
+                        uint32_t flags)
 {
     nao_status st = check_ctx(c);
     if (st != NAO_OK) return st;
     if ((st = check_prec(c, prec)) != NAO_OK) return st;
     if (n_work < 0 || (n_work > 0 && !work)) return (set_err(c, "bad work list"), NAO_ERR_INVALID_ARG);
     if (flags & ~NAO_RUN_CAPTURE_GRAPH) return (set_err(c, "unknown flags"), NAO_ERR_INVALID_ARG);
+    const bool capture = (flags & NAO_RUN_CAPTURE_GRAPH) != 0;
+    bool electrons = false;
     for (int64_t k = 0; k < n_work; ++k) {
         const nao_work& w = work[k];
         if (!w.sys || w.sys->ctx->device != c->device)
             return (set_err(c, "work entry with a system on another device"), NAO_ERR_INVALID_ARG);
-        if ((flags & NAO_RUN_CAPTURE_GRAPH) && w.sys->ctx != c)
+        if (capture && w.sys->ctx != c)
             return (set_err(c, "graph capture needs every system to belong to the context"), NAO_ERR_INVALID_ARG);
         if (w.op != 0 && w.op != 1) return (set_err(c, "work op must be 0 (H) or 1 (density)"), NAO_ERR_INVALID_ARG);
         const bool need_in = w.op == 0 ? w.sys->n_points > 0 : w.sys->basis.n_basis > 0;
         if ((need_in && !w.in) || !w.out) return (set_err(c, "NULL work pointer"), NAO_ERR_INVALID_ARG);
+        if (w.n_electrons && w.op != 1) return (set_err(c, "n_electrons is for density entries"), NAO_ERR_INVALID_ARG);
+        electrons = electrons || w.n_electrons;
     }
+    if (electrons && capture)
+        return (set_err(c, "n_electrons cannot be written by a captured graph"), NAO_ERR_INVALID_ARG);
     if (n_work == 0) return NAO_OK;
+    // another stream: it waits for the context's work, and the context's stream for it
+    hipStream_t own = c->stream, user = hip_stream ? static_cast<hipStream_t>(hip_stream) : own;
+    if (user != own) {
+        hipEvent_t ev = take_event(c);
+        if (!ev) return (set_err(c, "event creation failed"), NAO_ERR_HIP);
+        HIP_TRY(c, hipEventRecord(ev, own));
+        HIP_TRY(c, hipStreamWaitEvent(user, ev, 0));
+        c->pool.push_back(ev);
+        c->stream = user;
+    }
     try {
-        return run_many_impl(c, work, n_work, prec, (flags & NAO_RUN_CAPTURE_GRAPH) != 0);
+        st = run_many_impl(c, work, n_work, prec, capture);
+        for (int64_t k = 0; st == NAO_OK && k < n_work; ++k) {
+            const nao_work& w = work[k];
+            if (!w.n_electrons) continue;
+            const hipError_t e = launch_weighted_sum(w.sys->d_pw.as<double>(), w.sys->d_perm.as<int32_t>(), w.out,
+                                                     w.sys->n_points, c->wsum, c->wsum + WSUM_BLOCKS, c->stream);
+            if (e == hipSuccess)
+                (void)hipMemcpyAsync(w.n_electrons, c->wsum + WSUM_BLOCKS, sizeof(double), hipMemcpyDeviceToHost,
+                                     c->stream);
+            if (e != hipSuccess) st = hip_fail(c, e, "electron count");
+        }
+        if (st == NAO_OK && electrons) {
+            const hipError_t e = hipStreamSynchronize(c->stream);
+            if (e != hipSuccess) st = hip_fail(c, e, "nao_run_many");
+        }
     } catch (const std::bad_alloc&) {
         set_err(c, "host allocation failed");
-        return NAO_ERR_OUT_OF_MEMORY;
+        st = NAO_ERR_OUT_OF_MEMORY;
     }
+    if (user != own) {
+        c->stream = own;
+        hipEvent_t ev = take_event(c);
+        if (!ev) return (set_err(c, "event creation failed"), NAO_ERR_HIP);
+        HIP_TRY(c, hipEventRecord(ev, user));
+        HIP_TRY(c, hipStreamWaitEvent(own, ev, 0));
+        c->pool.push_back(ev);
+    }
+    return st;
 }
 
 }  // extern "C"

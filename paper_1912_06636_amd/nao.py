@@ -48,7 +48,7 @@ class BasisDesc(ctypes.Structure):
 
 
 class Work(ctypes.Structure):
-    _fields_ = [("sys", _vp), ("op", ctypes.c_int32), ("input", _vp), ("output", _vp)]
+    _fields_ = [("sys", _vp), ("op", ctypes.c_int32), ("input", _vp), ("output", _vp), ("n_electrons", _c_dp)]
 
 
 def _sig(name, res, *args):
@@ -93,7 +93,7 @@ _sig("nao_pulay_forces", _S, _vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp
 _sig("nao_integrate_h_ks", _S, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int)
 _sig("nao_integrate_h_gga", _S, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int)
 _sig("nao_system_destroy", None, _vp)
-_sig("nao_run_many", _S, _vp, ctypes.POINTER(Work), ctypes.c_int64, ctypes.c_int, ctypes.c_uint32)
+_sig("nao_run_many", _S, _vp, ctypes.POINTER(Work), ctypes.c_int64, ctypes.c_int, _vp, ctypes.c_uint32)
 _sig("nao_server_create", _S, _vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int, ctypes.POINTER(_vp))
 _sig("nao_server_open_session", _S, _vp, ctypes.POINTER(BasisDesc), ctypes.c_int64, _c_dp, _c_dp, ctypes.c_int32,
      _c_i64p)
@@ -266,19 +266,26 @@ class Context:
             out[nm] = (int(cnt[k]), float(ms[k]))
         return out
 
-    def run_many(self, work, precision="fp64", capture_graph=False):
-        """nao_run_many over [(system, op, input_tensor, output_tensor)], op 'h' or 'n'."""
+    def run_many(self, work, precision="fp64", capture_graph=False, stream=None, electrons=False):
+        """nao_run_many over [(system, op, input_tensor, output_tensor)], op 'h' or 'n'.  stream: a
+        hipStream_t (int) to run on instead of the context's.  electrons=True returns N_e of every
+        density entry (in work order) and synchronizes."""
         arr = (Work * len(work))()
         keep = []
+        ne = np.zeros(len(work), np.float64)
         for k, (sys_, op, x, y) in enumerate(work):
             px, sx, kx = _ptr_space(x)
             py, sy, ky = _ptr_space(y)
             if sx != MEM_DEVICE or sy != MEM_DEVICE:
                 raise ValueError("run_many takes device tensors only")
             keep += [kx, ky]
-            arr[k] = Work(sys_.handle, 0 if op == "h" else 1, px, py)
+            pe = ne[k:].ctypes.data_as(_c_dp) if electrons and op == "n" else None
+            arr[k] = Work(sys_.handle, 0 if op == "h" else 1, px, py, pe)
         _check(_lib.nao_run_many(self.handle, arr, len(work), PRECISIONS[precision],
+                                 _vp(stream) if stream else None,
                                  RUN_CAPTURE_GRAPH if capture_graph else 0), self.handle)
+        if electrons:
+            return [float(ne[k]) for k, wk in enumerate(work) if wk[1] == "n"]
 
 
 def build_batches(ctx, basis, xyz, w, max_batch, batcher="octree"):

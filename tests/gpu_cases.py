@@ -19,6 +19,16 @@ def rel_max(got, ref):
     return float(np.max(np.abs(got - ref))) / (den if den > 0 else 1.0) if ref.size else 0.0
 
 
+def _finish(basis, xyz, rp, n_r, n_ang, seed, n_occ, max_batch):
+    """Grid, potential and density matrix D = C C^T for a test structure."""
+    X, wt, _ = g.make_grid(xyz, rp, n_r, n_ang)
+    v = g.gaussian_potential(X, 6, xyz.min(0), xyz.max(0), g.rng_for(7, seed, 2))
+    nb = g.n_basis(basis)
+    C = g.rng_for(7, seed, 3).normal(size=(nb, n_occ))
+    D = C @ C.T
+    return dict(basis=basis, xyz=X, w=wt, v=v, D=0.5 * (D + D.T), C=C, max_batch=max_batch, n_basis=nb)
+
+
 @functools.lru_cache(maxsize=None)
 def case(name):
     """Small/medium workloads (oracle runs in seconds) with full oracle references."""
@@ -40,6 +50,27 @@ def case(name):
         C = g.rng_for(7, 0, 3).normal(size=(nb, 6))
         D = C @ C.T
         w = dict(basis=basis, xyz=X, w=wt, v=v, D=0.5 * (D + D.T), C=C, max_batch=64, n_basis=nb)
+    elif name == "two_species_8":
+        # two species with 8 radial functions each (the shape of a two-element slab basis): a
+        # 16 x 199 x 4 spline table, more than the basis kernel stages on chip
+        xyz = g.geometry_sc_first_n(6, 2.3, 0.1, g.rng_for(7, 8, 0))
+        basis = g.make_basis(xyz, np.array([0, 1, 0, 1, 0, 1], np.int32),
+                             [(0, 0, 1, 1, 1, 2, 2, 3), (0, 0, 1, 1, 2, 2, 3, 3)], [5.0, 4.0], 7, 8)
+        w = _finish(basis, xyz, 5.0, 12, 50, seed=8, n_occ=12, max_batch=128)
+    elif name == "dense_cluster":
+        # 343 atoms 0.5 A apart with one s function each: the units near the centre see every
+        # atom, more than the basis kernel stages on chip
+        k = np.arange(7) * 0.5
+        xyz = np.array([[x, y, z] for z in k for y in k for x in k])
+        basis = g.make_basis(xyz, np.zeros(len(xyz), np.int32), [(0,)], [3.0], 7, 9)
+        w = _finish(basis, xyz, 3.0, 2, 6, seed=9, n_occ=30, max_batch=64)
+    elif name == "many_species":
+        # nine species of 15 shells each: 135 shells, more than the basis kernel stages on chip
+        xyz = np.array([[1.6 * i, 1.6 * j, 0.0] for j in range(3) for i in range(3)])
+        xyz = xyz + g.rng_for(7, 10, 0).normal(scale=0.1, size=xyz.shape)
+        shells = (0, 0, 0, 0, 0, 1, 1, 1, 1, 1, 0, 0, 0, 0, 0)
+        basis = g.make_basis(xyz, np.arange(9, dtype=np.int32), [shells] * 9, [3.5] * 9, 7, 10)
+        w = _finish(basis, xyz, 3.5, 10, 26, seed=10, n_occ=20, max_batch=128)
     else:
         raise KeyError(name)
     B = ob.Basis(w["basis"])

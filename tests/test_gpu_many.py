@@ -118,3 +118,71 @@ def test_many_with_wide_tiles(env):
         assert rel_max(H.cpu().numpy(), s.integrate_h(w["v"])) <= 1e-12
     structs[1][1].set_h_tile(64)
     structs[3][1].set_h_tile(64)
+
+
+def test_graph_dropped_when_scratch_grows():
+    """A captured launch plan holds the address of the context's basis scratch.  Building a
+    system with larger blocks on the same context replaces that scratch; a later replay of the
+    same argument set must run a fresh capture (results equal the oracle), not the old graph."""
+    import torch
+    from paper_1912_06636_amd import nao
+    say("graph after scratch growth")
+    ctx = nao.Context(0)
+    w1, B1, ref1 = case("config1")
+    s1 = nao.build_batches(ctx, w1["basis"], w1["xyz"], w1["w"], w1["max_batch"])
+    v1, D1, H1, n1 = _tensors(torch, w1, s1)
+    work = [(s1, "h", v1, H1), (s1, "n", D1, n1)]
+    ctx.run_many(work, capture_graph=True)
+    ctx.synchronize()
+    assert rel_max(H1.cpu().numpy(), ref1["H"]) <= 1e-12
+    used0, _ = ctx.memory()
+    w2, B2, ref2 = case("multitile")     # larger basis blocks: the scratch is reallocated
+    s2 = nao.build_batches(ctx, w2["basis"], w2["xyz"], w2["w"], w2["max_batch"])
+    for rep in range(3):
+        H1.fill_(5.0)
+        n1.fill_(-1.0)
+        torch.cuda.synchronize()
+        ctx.run_many(work, capture_graph=True)
+        ctx.synchronize()
+        assert rel_max(H1.cpu().numpy(), ref1["H"]) <= 1e-12, rep
+        assert rel_max(n1.cpu().numpy(), ref1["n"]) <= 1e-12, rep
+    # the larger system's own results stay exact, alone and together with the first
+    v2, D2, H2, n2 = _tensors(torch, w2, s2)
+    ctx.run_many(work + [(s2, "h", v2, H2), (s2, "n", D2, n2)], capture_graph=True)
+    ctx.synchronize()
+    assert rel_max(H2.cpu().numpy(), ref2["H"]) <= 1e-12 and rel_max(n2.cpu().numpy(), ref2["n"]) <= 1e-12
+    assert rel_max(H1.cpu().numpy(), ref1["H"]) <= 1e-12
+    assert used0 > 0
+    s2.close()
+    s1.close()
+    ctx.close()
+
+
+def test_many_on_a_caller_stream_with_electron_counts(env):
+    """hip_stream and per-entry n_electrons: the work runs on the caller's stream, after the
+    context's earlier work; N_e of every density entry equals the single-call value."""
+    nao, ctx, structs, torch = env
+    say("run_many on a caller stream with electron counts")
+    tens = [_tensors(torch, w, s) for w, s in structs]
+    work = []
+    for (w, s), (v, D, H, n) in zip(structs, tens):
+        work += [(s, "n", D, n), (s, "h", v, H)]
+    st = torch.cuda.Stream()
+    ne = ctx.run_many(work, stream=st.cuda_stream, electrons=True)
+    assert len(ne) == len(structs)
+    for (w, s), (v, D, H, n), ne_k in zip(structs, tens, ne):
+        ns, Ne = s.update_density(w["D"], electrons=True)
+        assert rel_max(n.cpu().numpy(), ns) <= 1e-12
+        assert abs(ne_k - Ne) <= 1e-12 * abs(Ne)
+        assert rel_max(H.cpu().numpy(), s.integrate_h(w["v"])) <= 1e-12
+    # the context's stream orders after the caller-stream work: overwrite and rerun eagerly
+    for v, D, H, n in tens:
+        H.fill_(3.0)
+    torch.cuda.synchronize()
+    ctx.run_many([(s, "h", v, H) for (w, s), (v, D, H, n) in zip(structs, tens)], stream=st.cuda_stream)
+    ctx.synchronize()
+    st.synchronize()
+    for (w, s), (v, D, H, n) in zip(structs, tens):
+        assert rel_max(H.cpu().numpy(), s.integrate_h(w["v"])) <= 1e-12
+    with pytest.raises(nao.NaoError):
+        ctx.run_many(work, capture_graph=True, electrons=True)

@@ -149,6 +149,25 @@ def test_density_reads_upper_triangle(nao, ctx):
     s.close()
 
 
+def test_nonsymmetric_density_matrix_reads_upper_triangle(nao, ctx):
+    """For a D that is not symmetric the result is that of the symmetric matrix whose upper
+    triangle is D's (the lower triangle is never read), for the density and its gradient."""
+    w, B, ref = case("two_species")
+    say("non-symmetric D")
+    rng = np.random.default_rng(77)
+    D = rng.normal(size=w["D"].shape)
+    Du = oi.symmetric_from_upper(D)
+    s = nao.build_batches(ctx, w["basis"], w["xyz"], w["w"], w["max_batch"])
+    n_ref = oi.density(B, w["xyz"], Du)
+    assert rel_max(s.update_density(D), n_ref) <= TOL
+    n, gn = s.update_density_gradient(D)
+    n2, g_ref = oi.density_gradient(B, w["xyz"], Du)
+    assert rel_max(n, n_ref) <= TOL and rel_max(gn, g_ref) <= TOL
+    # not (D + D^T) / 2: that reading gives a different density here
+    assert rel_max(oi.density(B, w["xyz"], 0.5 * (D + D.T)), n_ref) > 1e-3
+    s.close()
+
+
 def test_device_memspace_matches_host(nao, ctx):
     import torch
     w, B, ref = case("multitile")

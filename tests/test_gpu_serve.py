@@ -1,12 +1,16 @@
-"""Serving core on the GPU: each request's result is the same alone and in a mix of
-concurrently admitted structures; admission respects the HBM budget (sessions wait for
-memory, then run); closed sessions free their memory."""
+"""Serving core on the GPU: served results equal the FP64 oracle's (first iteration with its
+own potential, second iteration with a fresh D and the kept potential); each request's result
+is the same alone and in a mix of concurrently admitted structures, in every precision;
+admission respects the HBM budget (sessions wait for memory, then run); closed sessions free
+their memory; a result is readable until its session's next request starts."""
 import sys
 import time
 
 import numpy as np
 import pytest
 
+from oracle import basis as ob
+from oracle import integrals as oi
 from tests.gpu_cases import rel_max
 from workloads import generate as g
 
@@ -43,7 +47,46 @@ def drain(srv, tickets, timeout=120.0):
         time.sleep(0.0005)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+# Stated normwise bounds against FP64 of the batched precisions (the serving default is fp32).
+SERVE_TOL = {"fp64": 1e-12, "fp32": 1e-6, "bf16x3": 3e-5, "bf16x6": 1e-6}
+
+
+def test_served_results_match_oracle(lib):
+    """Two iterations of one session against the oracle: (D1, v) then (D2, kept v)."""
+    say("serve vs oracle")
+    w = small(40, 14)
+    B = ob.Basis(w["basis"])
+    rng = np.random.default_rng(41)
+    C2 = rng.normal(size=(w["n_basis"], 20))
+    D2 = C2 @ C2.T
+    H_ref = oi.hamiltonian(B, w["xyz"], w["w"], w["v"])
+    n1_ref = oi.density(B, w["xyz"], w["D"])
+    n2_ref = oi.density(B, w["xyz"], D2)
+    home = lib.Context(0)
+    srv = lib.Server(home, n_slots=2, max_per_launch=4, precision="fp64")
+    sid = srv.open_session(w["basis"], w["xyz"], w["w"], 256)
+    nb, npt = w["n_basis"], len(w["xyz"])
+    t1 = srv.submit(sid, w["D"], w["v"])
+    drain(srv, [t1])
+    H1, n1 = np.empty((nb, nb)), np.empty(npt)
+    srv.result(t1, H1, n1)
+    say("serve vs oracle", "iteration 1: e_H %.2e e_n %.2e" % (rel_max(H1, H_ref), rel_max(n1, n1_ref)))
+    assert rel_max(H1, H_ref) <= 1e-12 and rel_max(n1, n1_ref) <= 1e-12
+    t2 = srv.submit(sid, D2)                          # fresh D, the potential of iteration 1
+    drain(srv, [t2])
+    H2, n2 = np.empty((nb, nb)), np.empty(npt)
+    srv.result(t2, H2, n2)
+    say("serve vs oracle", "iteration 2: e_H %.2e e_n %.2e" % (rel_max(H2, H_ref), rel_max(n2, n2_ref)))
+    assert rel_max(H2, H_ref) <= 1e-12 and rel_max(n2, n2_ref) <= 1e-12
+    # iteration 1's result was replaced by iteration 2's: the server says so
+    with pytest.raises(lib.NaoError) as e:
+        srv.result(t1, H1, n1)
+    assert e.value.status == lib.ERR_INVALID_ARG
+    srv.close()
+    home.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "bf16x6"])
 def test_alone_equals_mix(lib, prec):
     say("serve alone vs mix", prec)
     works = [small(k, n) for k, n in enumerate([9, 14, 20, 6, 12])]
@@ -68,6 +111,12 @@ def test_alone_equals_mix(lib, prec):
     srv.result(tks[0], H_mix, n_mix)
     tol = 1e-12 if prec == "fp64" else 1e-6
     assert rel_max(H_mix, H_alone) <= tol and rel_max(n_mix, n_alone) <= tol
+    # and against the oracle, within the precision's stated bound
+    B0 = ob.Basis(works[0]["basis"])
+    eH = rel_max(H_mix, oi.hamiltonian(B0, works[0]["xyz"], works[0]["w"], works[0]["v"]))
+    en = rel_max(n_mix, oi.density(B0, works[0]["xyz"], works[0]["D"]))
+    say("serve alone vs mix", prec, "vs oracle: e_H %.2e e_n %.2e" % (eH, en))
+    assert eH <= SERVE_TOL[prec] and en <= SERVE_TOL[prec]
     # the other members against their own single-call results
     for s, w, t in zip(sids[1:], works[1:], tks[1:]):
         sysm = lib.build_batches(home, w["basis"], w["xyz"], w["w"], 256)
@@ -108,6 +157,12 @@ def test_admission_by_budget_and_iterations(lib):
     st1, st2 = srv.poll(t1), srv.poll(t2)
     assert st1[3] <= st2[2] + 1e-9                    # iterations of one session run in order
     assert srv.poll(t3)[0] == 0                       # still waiting for memory
+    H0 = np.empty((works[0]["n_basis"],) * 2)
+    with pytest.raises(lib.NaoError):                 # t2 replaced t1's result
+        srv.result(t1, H0)
+    srv.result(t2, H0)
+    B0 = ob.Basis(works[0]["basis"])
+    assert rel_max(H0, oi.hamiltonian(B0, works[0]["xyz"], works[0]["w"], works[0]["v"])) <= 1e-12
     srv.close_session(sids[0])
     drain(srv, [t3])
     assert srv.session_info(sids[1])["resident"]
