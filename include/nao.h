@@ -245,6 +245,26 @@ nao_status nao_eval_basis(nao_system sys, int64_t batch_begin, int64_t batch_end
  * ------------------------------------------------------------------------------------- */
 nao_status nao_integrate_h(nao_system sys, const double* v, nao_memspace v_space,
                            nao_precision precision, double* H, nao_memspace H_space);
+/* ---------------------------------------------------------------------------------------
+ * nao_integrate_h without any device allocation, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same result as nao_integrate_h (up to the order of the FP64 accumulation)
+ * and the same kernels; v [n_points] and H [N_b][N_b] must be device memory of the
+ * context's GPU, and the call only enqueues.
+ * Scratch: instead of the context's basis-value buffer, the call uses one fixed array of
+ * 256 MiB per GPU inside the library (held from the first context on that GPU until the
+ * process ends): a segment table, w*v (8 bytes per point) and the basis values of as many
+ * execution groups at a time as fit.  NAO_ERR_INVALID_ARG, with nothing enqueued, when
+ * w*v of n_points > 255 MiB / 8 (about 33 million points) does not fit beside the table,
+ * when one execution group's basis values do not fit what is left, or when the sub-blocks
+ * outnumber the table.  The call allocates nothing (no hipMalloc, hipFree, events or
+ * library allocations), so it is also slower than nao_integrate_h on large systems (more,
+ * smaller launches).
+ * Every call on one GPU shares that GPU's array and leaves its contents behind: two calls
+ * whose work overlaps on one GPU (other streams, other contexts, other host threads) race
+ * and give wrong results; order them on one stream or synchronize between them.
+ * ------------------------------------------------------------------------------------- */
+nao_status nao_integrate_h_noalloc(nao_system sys, const double* v, nao_precision precision, double* H);
 
 /* ---------------------------------------------------------------------------------------
  * Density n(r_p) = sum_ij phi_i(r_p) D_ij phi_j(r_p) at every point (eq. Density), batch by

@@ -133,4 +133,16 @@ hipError_t launch_weighted_sum(const double* pw, const int32_t* perm, const doub
                                int64_t n_points, double* partial, double* out, hipStream_t st);
 constexpr int WSUM_BLOCKS = 1024;
 
+// Fixed per-GPU scratch of the allocation-free Hamiltonian call (kernels.hip): a file-scope
+// device array of NOALLOC_SCRATCH_BYTES that the library never allocates or frees.  Its head
+// (NOALLOC_SEG_BYTES) holds the call's segment table, then w*v, then the basis values of one
+// sub-block of execution groups at a time.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)256 << 20;
+constexpr size_t NOALLOC_SEG_BYTES = (size_t)1 << 20;
+// Look up the array's device address on `device`, which must be the current device; once per
+// device (later calls return at once).  Called by nao_ctx_create.
+hipError_t noalloc_scratch_init(int device);
+// The address found by noalloc_scratch_init on `device`, or nullptr before it succeeded.
+void* noalloc_scratch(int device);
+
 }  // namespace nao

@@ -8,6 +8,7 @@
 //   - D and H dense row-major [N_b][N_b] FP64; n in the caller's point order.
 #include <algorithm>
 #include <atomic>
+#include <mutex>
 #include <type_traits>
 
 #include <hip/hip_runtime.h>
@@ -1639,6 +1640,43 @@ hipError_t launch_weighted_sum(const double* pw, const int32_t* perm, const doub
                        partial);
     hipLaunchKernelGGL(wsum_final_kernel, dim3(1), dim3(256), 0, st, partial, WSUM_BLOCKS, out);
     return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
+// Scratch of the allocation-free Hamiltonian call.  Every GPU that loads this code object holds
+// its own copy of the array until the process ends.  In host code `scratch` names a host-side
+// stand-in, not device memory: the device address is looked up once per device and kept in
+// g_noalloc_ptr, and only that address is ever handed to kernels or copies.
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[NOALLOC_MAX_DEVICES] = {};
+}  // namespace
+
+hipError_t noalloc_scratch_init(int device)
+{
+    if (device < 0 || device >= NOALLOC_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (g_noalloc_ptr[device]) return hipSuccess;
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device) return hipErrorInvalidDevice;  // the caller makes `device` current first
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_noalloc_ptr[device] = ptr;
+    return hipSuccess;
+}
+
+void* noalloc_scratch(int device)
+{
+    if (device < 0 || device >= NOALLOC_MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    return g_noalloc_ptr[device];
 }
 
 }  // namespace nao

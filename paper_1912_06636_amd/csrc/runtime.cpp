@@ -277,6 +277,11 @@ struct nao_system_s {
     // groups
     std::vector<Block> blocks;
     int64_t n_units = 0, n_h_items = 0, n_n_items = 0;
+    // host copies for the allocation-free Hamiltonian call: every unit, the first 64-wide
+    // Hamiltonian item of every unit (n_units + 1 entries), and that call's segment table
+    std::vector<DevUnit> h_units;
+    std::vector<int64_t> h_item_first;
+    std::vector<DevSeg> na_segs;
     // device state
     DevSys dsys{};
     DevArray d_sys, d_px, d_py, d_pz, d_pw, d_perm, d_atoms, d_species, d_shell_ptr, d_shell_l, d_shell_rad,
@@ -359,6 +364,7 @@ nao_status build_groups(nao_system_s* s)
     std::vector<int32_t> ufn;
     std::vector<HItem> hitems, hwitems;
     std::vector<NItem> nitems;
+    std::vector<int64_t> item_first;
     s->blocks.clear();
     Block cur;
     int64_t off = 0;
@@ -392,6 +398,7 @@ nao_status build_groups(nao_system_s* s)
         off += elems;
         cur.phi_elems = off;
         cur.unit_count++;
+        item_first.push_back((int64_t)hitems.size());
         const int nt = (d.m + TILE - 1) / TILE;  // tiles that hold at least one column
         for (int tj = 0; tj < nt; ++tj) {
             for (int ti = 0; ti <= tj; ++ti) hitems.push_back(HItem{(int32_t)k, (int16_t)ti, (int16_t)tj});
@@ -407,6 +414,7 @@ nao_status build_groups(nao_system_s* s)
         cur.n_count = (int64_t)nitems.size() - cur.n_begin;
     }
     if (cur.unit_count) s->blocks.push_back(cur);
+    item_first.push_back((int64_t)hitems.size());
     s->n_units = (int64_t)units.size();
     s->n_h_items = (int64_t)hitems.size();
     s->n_n_items = (int64_t)nitems.size();
@@ -424,6 +432,8 @@ nao_status build_groups(nao_system_s* s)
     for (const Block& b : s->blocks) need = std::max(need, (size_t)b.phi_elems);
     if ((st = grow_scratch(c, need)) != NAO_OK) return st;
     HIP_TRY(c, hipStreamSynchronize(c->stream));
+    s->h_units = std::move(du);
+    s->h_item_first = std::move(item_first);
     return resident_layout(s);
 }
 
@@ -811,6 +821,7 @@ nao_status nao_ctx_create(int device, void* hip_stream, size_t hbm_budget_bytes,
     }
     c->scratch_cap_elems = scratch_cap_from_env();
     e = hipSetDevice(device);
+    if (e == hipSuccess) e = noalloc_scratch_init(device);  // the device address of the fixed scratch
     if (e == hipSuccess) {
         if (hip_stream) {
             c->stream = static_cast<hipStream_t>(hip_stream);
@@ -1450,6 +1461,81 @@ nao_status nao_integrate_h(nao_system s, const double* v, nao_memspace v_space, 
         HIP_TRY(c, hipStreamSynchronize(c->stream));
     }
     if (v_space == NAO_MEM_HOST) HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return NAO_OK;
+}
+
+nao_status nao_integrate_h_noalloc(nao_system s, const double* v, nao_precision prec, double* H)
+{
+    if (!s) return (g_thread_error = "system is NULL", NAO_ERR_INVALID_ARG);
+    nao_ctx c = s->ctx;
+    nao_status st = check_ctx(c);
+    if (st != NAO_OK) return st;
+    if ((st = check_prec(c, prec)) != NAO_OK) return st;
+    const int64_t n = s->n_points, nb = s->basis.n_basis;
+    if (!H || (n > 0 && !v)) return (set_err(c, "NULL v or H"), NAO_ERR_INVALID_ARG);
+    char* base = static_cast<char*>(noalloc_scratch(c->device));
+    if (!base) return (set_err(c, "the fixed scratch of this device was not set up"), NAO_ERR_NOT_READY);
+    // layout of the fixed scratch: segment table | w*v | basis values of one sub-block
+    const size_t wv_bytes = ((size_t)std::max<int64_t>(1, n) * sizeof(double) + 255) / 256 * 256;
+    if (NOALLOC_SEG_BYTES + wv_bytes >= NOALLOC_SCRATCH_BYTES)
+        return (set_err(c, "n_points = " + std::to_string(n) + " needs " + std::to_string(wv_bytes) +
+                               " B of w*v, more than the fixed scratch of " +
+                               std::to_string(NOALLOC_SCRATCH_BYTES) + " B holds"),
+                NAO_ERR_INVALID_ARG);
+    const size_t esz = prec == NAO_FP64 ? sizeof(double) : sizeof(float);
+    double* wv = reinterpret_cast<double*>(base + NOALLOC_SEG_BYTES);
+    const uintptr_t phi0 = reinterpret_cast<uintptr_t>(base + NOALLOC_SEG_BYTES + wv_bytes);
+    const int64_t cap = (int64_t)((NOALLOC_SCRATCH_BYTES - NOALLOC_SEG_BYTES - wv_bytes) / esz);
+    if (s->h_units.size() != (size_t)s->n_units || s->h_item_first.size() != (size_t)s->n_units + 1)
+        return (set_err(c, "system has no unit table"), NAO_ERR_INTERNAL);
+    // sub-blocks: runs of consecutive units of one block whose basis values fit the fixed
+    // scratch; phi of a sub-block is placed so that its first unit's values start at phi0
+    std::vector<DevSeg>& segs = s->na_segs;
+    segs.clear();
+    for (const Block& b : s->blocks) {
+        int64_t u = b.unit_begin;
+        const int64_t uend = b.unit_begin + b.unit_count;
+        while (u < uend) {
+            const int64_t o0 = s->h_units[u].out_offset;
+            int64_t u1 = u;
+            while (u1 < uend) {
+                const DevUnit& d = s->h_units[u1];
+                if (d.out_offset + (int64_t)d.n_points * d.ld - o0 > cap) break;
+                ++u1;
+            }
+            if (u1 == u)
+                return (set_err(c, "an execution group's basis values (" +
+                                       std::to_string((int64_t)s->h_units[u].n_points * s->h_units[u].ld * (int64_t)esz) +
+                                       " B) exceed the fixed scratch"),
+                        NAO_ERR_INVALID_ARG);
+            DevSeg g = make_seg(s, b, true, false);
+            g.phi = reinterpret_cast<void*>(phi0 - (uintptr_t)o0 * esz);
+            g.unit_begin = u;
+            g.unit_count = u1 - u;
+            g.item_begin = s->h_item_first[u];
+            g.item_count = s->h_item_first[u1] - s->h_item_first[u];
+            g.wv = wv;
+            g.H = H;
+            segs.push_back(g);
+            u = u1;
+        }
+    }
+    if (segs.size() * sizeof(DevSeg) > NOALLOC_SEG_BYTES)
+        return (set_err(c, std::to_string(segs.size()) + " sub-blocks exceed the segment table of the fixed scratch"),
+                NAO_ERR_INVALID_ARG);
+    // no profiling events here: nothing in this call creates or allocates anything
+    const Mode mode = exec_mode(c, prec);
+    HIP_TRY(c, launch_fill(H, nb * nb, 0.0, c->stream));
+    if (n > 0) HIP_TRY(c, launch_wv(s->d_pw.as<double>(), s->d_perm.as<int32_t>(), v, wv, n, c->stream));
+    if (!segs.empty()) {
+        HIP_TRY(c, hipMemcpyAsync(base, segs.data(), segs.size() * sizeof(DevSeg), hipMemcpyHostToDevice, c->stream));
+        const DevSeg* dseg = reinterpret_cast<const DevSeg*>(base);
+        for (size_t k = 0; k < segs.size(); ++k) {
+            HIP_TRY(c, launch_basis(dseg + k, 1, segs[k].unit_count, s->spline_lds, prec != NAO_FP64, c->stream));
+            HIP_TRY(c, launch_h(mode, dseg + k, 1, segs[k].item_count, c->stream, 0, TILE));
+        }
+    }
+    HIP_TRY(c, launch_mirror(H, nb, c->stream));
     return NAO_OK;
 }
 

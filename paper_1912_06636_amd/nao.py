@@ -87,6 +87,7 @@ _sig("nao_get_batches", _S, _vp, _c_i64p, _c_i64p, _c_i64p, _c_i32p)
 _sig("nao_system_work", _S, _vp, _c_dp)
 _sig("nao_eval_basis", _S, _vp, ctypes.c_int64, ctypes.c_int64, _vp, ctypes.c_int, _c_i64p)
 _sig("nao_integrate_h", _S, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int)
+_sig("nao_integrate_h_noalloc", _S, _vp, _vp, ctypes.c_int, _vp)
 _sig("nao_update_density", _S, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int, _c_dp)
 _sig("nao_update_density_gradient", _S, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_int)
 _sig("nao_pulay_forces", _S, _vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int)
@@ -112,7 +113,7 @@ EXPORTED = [
     "nao_plan_destroy", "nao_build_batches", "nao_system_set_group_max", "nao_system_set_h_tile", "nao_system_autotune", "nao_system_info", "nao_get_batches",
     "nao_system_work", "nao_eval_basis", "nao_integrate_h", "nao_update_density", "nao_update_density_gradient", "nao_integrate_h_gga",
     "nao_pulay_forces", "nao_integrate_h_ks", "nao_plan_create_ex", "nao_build_batches_ex",
-    "nao_system_set_resident_basis",
+    "nao_system_set_resident_basis", "nao_integrate_h_noalloc",
     "nao_system_destroy",
     "nao_run_many", "nao_server_create", "nao_server_open_session", "nao_server_close_session",
     "nao_server_session_info", "nao_server_submit", "nao_server_step", "nao_server_poll", "nao_server_result",
@@ -383,6 +384,15 @@ class System:
             out = np.empty((self.n_basis, self.n_basis), np.float64)
         ph, sh, kh = _ptr_space(out)
         _check(_lib.nao_integrate_h(self.handle, pv, sv, PRECISIONS[precision], ph, sh), self.ctx.handle)
+        return out
+
+    def integrate_h_noalloc(self, v, out, precision="fp64"):
+        """nao_integrate_h_noalloc: H into out; v and out must be device tensors."""
+        pv, sv, kv = _ptr_space(v)
+        ph, sh, kh = _ptr_space(out)
+        if sv != MEM_DEVICE or sh != MEM_DEVICE:
+            raise ValueError("nao_integrate_h_noalloc takes device memory only")
+        _check(_lib.nao_integrate_h_noalloc(self.handle, pv, PRECISIONS[precision], ph), self.ctx.handle)
         return out
 
     def update_density(self, D, precision="fp64", out=None, electrons=False):
