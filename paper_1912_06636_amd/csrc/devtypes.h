@@ -25,7 +25,7 @@ struct DevSys {
     const int32_t* shell_l;            // [n_shells]
     const int32_t* shell_radial;       // [n_shells]
     const double* radial_par;          // [n_radial][4]: rmin, rcut^2, 1/Delta, ln(rmin)
-    const double* spline;              // [n_radial][n_knots-1][4] polynomial coefficients
+    const double* spline;              // [n_radial][n_knots][2]: y_k, M_k / 6 (plan.h)
     const int32_t* species_fn_ptr;     // [n_species+1] into fn_code
     const int32_t* fn_code;            // per species function: (shell within species << 4) | lm
     int32_t n_species;

@@ -67,41 +67,50 @@ __device__ inline double dist2_exact(double dx, double dy, double dz)
     return (xx + yy) + zz;
 }
 
-// Real orthonormal spherical harmonics (l <= 3) of a unit vector, m = -l..l; Y_11 ~ +x.
+// Real orthonormal spherical harmonics of degree L (<= 3) of a unit vector, m = -L..L, into
+// Y[0 .. 2L]; Y_11 ~ +x.
+template <int L>
+__device__ inline void ylm_l(double x, double y, double z, double* Y)
+{
+    if constexpr (L == 0) {
+        Y[0] = 0.28209479177387814;  // 1 / (2 sqrt(pi))
+    } else if constexpr (L == 1) {
+        const double c1 = 0.48860251190291992;  // sqrt(3 / (4 pi))
+        Y[0] = c1 * y;
+        Y[1] = c1 * z;
+        Y[2] = c1 * x;
+    } else if constexpr (L == 2) {
+        const double c2a = 1.0925484305920792;   // sqrt(15 / pi) / 2
+        const double c2b = 0.31539156525252005;  // sqrt(5 / pi) / 4
+        const double c2c = 0.54627421529603959;  // sqrt(15 / pi) / 4
+        Y[0] = c2a * x * y;
+        Y[1] = c2a * y * z;
+        Y[2] = c2b * (3.0 * z * z - 1.0);
+        Y[3] = c2a * x * z;
+        Y[4] = c2c * (x * x - y * y);
+    } else {
+        const double c3a = 0.59004358992664352;  // sqrt(35 / (2 pi)) / 4
+        const double c3b = 2.8906114426405538;   // sqrt(105 / pi) / 2
+        const double c3c = 0.45704579946446572;  // sqrt(21 / (2 pi)) / 4
+        const double c3d = 0.37317633259011546;  // sqrt(7 / pi) / 4
+        const double c3e = 1.4453057213202769;   // sqrt(105 / pi) / 4
+        Y[0] = c3a * y * (3.0 * x * x - y * y);
+        Y[1] = c3b * x * y * z;
+        Y[2] = c3c * y * (5.0 * z * z - 1.0);
+        Y[3] = c3d * (5.0 * z * z * z - 3.0 * z);
+        Y[4] = c3c * x * (5.0 * z * z - 1.0);
+        Y[5] = c3e * z * (x * x - y * y);
+        Y[6] = c3a * x * (x * x - 3.0 * y * y);
+    }
+}
+
+// All harmonics up to lmax (<= 3), index l^2 + l + m.
 __device__ inline void real_ylm(double x, double y, double z, int lmax, double* Y)
 {
-    const double c00 = 0.28209479177387814;   // 1 / (2 sqrt(pi))
-    const double c1 = 0.48860251190291992;    // sqrt(3 / (4 pi))
-    const double c2a = 1.0925484305920792;    // sqrt(15 / pi) / 2
-    const double c2b = 0.31539156525252005;   // sqrt(5 / pi) / 4
-    const double c2c = 0.54627421529603959;   // sqrt(15 / pi) / 4
-    const double c3a = 0.59004358992664352;   // sqrt(35 / (2 pi)) / 4
-    const double c3b = 2.8906114426405538;    // sqrt(105 / pi) / 2
-    const double c3c = 0.45704579946446572;   // sqrt(21 / (2 pi)) / 4
-    const double c3d = 0.37317633259011546;   // sqrt(7 / pi) / 4
-    const double c3e = 1.4453057213202769;    // sqrt(105 / pi) / 4
-    Y[0] = c00;
-    if (lmax >= 1) {
-        Y[1] = c1 * y;
-        Y[2] = c1 * z;
-        Y[3] = c1 * x;
-    }
-    if (lmax >= 2) {
-        Y[4] = c2a * x * y;
-        Y[5] = c2a * y * z;
-        Y[6] = c2b * (3.0 * z * z - 1.0);
-        Y[7] = c2a * x * z;
-        Y[8] = c2c * (x * x - y * y);
-    }
-    if (lmax >= 3) {
-        Y[9] = c3a * y * (3.0 * x * x - y * y);
-        Y[10] = c3b * x * y * z;
-        Y[11] = c3c * y * (5.0 * z * z - 1.0);
-        Y[12] = c3d * (5.0 * z * z * z - 3.0 * z);
-        Y[13] = c3c * x * (5.0 * z * z - 1.0);
-        Y[14] = c3e * z * (x * x - y * y);
-        Y[15] = c3a * x * (x * x - 3.0 * y * y);
-    }
+    ylm_l<0>(x, y, z, Y);
+    if (lmax >= 1) ylm_l<1>(x, y, z, Y + 1);
+    if (lmax >= 2) ylm_l<2>(x, y, z, Y + 4);
+    if (lmax >= 3) ylm_l<3>(x, y, z, Y + 9);
 }
 
 // Partial derivatives of the harmonic polynomials of real_ylm (index lm) with respect to the
@@ -139,9 +148,10 @@ __device__ inline void ylm_grad_one(int lm, double x, double y, double z, double
 // Basis evaluation
 constexpr size_t BASIS_LDS_BYTES = (size_t)MAX_SPLINE_LDS * sizeof(double);
 
-constexpr int BASIS_ATOMS = 256;   // atoms of a unit staged in LDS
+constexpr int BASIS_ATOMS = 192;   // atoms of a unit staged in LDS
 constexpr int BASIS_SHELLS = 128;  // shells of a system staged in LDS
 constexpr int BASIS_SLICES = 4;    // work items per unit (point slices) of the basis kernel
+constexpr int BASIS_WIN = 16;      // values per pair staged at a time for the row writes
 
 // Basis values of execution units: BASIS_SLICES workgroups per unit, each taking a contiguous
 // slice of the unit's points (more workgroups in flight than one per unit, and shorter tails);
@@ -150,10 +160,16 @@ constexpr int BASIS_SLICES = 4;    // work items per unit (point slices) of the 
 // parameters) are staged in LDS first, so that a pair's chain of table lookups stays on chip;
 // a unit or system larger than the staging arrays reads them from global memory instead.
 template <typename T, bool SPLINE_LDS, int EX>
-__global__ __launch_bounds__(256) void basis_kernel(const DevSeg* __restrict__ segs, int n_segs, int64_t total,
-                                                    int spline_lds)
+__global__ __launch_bounds__(256, 2) void basis_kernel(const DevSeg* __restrict__ segs, int n_segs, int64_t total,
+                                                       int spline_lds)
 {
     extern __shared__ double lds_spline[];
+    // plain basis values (EX = EXTRA_NONE): per wave, BASIS_WIN values of each of its 64 pairs,
+    // and per pair the unit-local offset of its first value and its value count
+    constexpr bool STAGE = EX == EXTRA_NONE;
+    __shared__ double s_win[STAGE ? 4 * 64 * (BASIS_WIN + 1) : 1];
+    __shared__ __align__(8) int32_t s_pair[STAGE ? 4 * 64 * 2 : 2];
+    __shared__ double s_pt[STAGE ? MAX_UNIT_POINTS / BASIS_SLICES : 1][3];  // the slice's points
     __shared__ double s_atom[BASIS_ATOMS][4];  // x, y, z, (largest cutoff)^2
     __shared__ int32_t s_aspc[BASIS_ATOMS][2];  // species, first column in the unit
     __shared__ double s_par[BASIS_SHELLS][4];  // rmin, rcut^2, 1/Delta, ln rmin of the shell's radial
@@ -161,6 +177,7 @@ __global__ __launch_bounds__(256) void basis_kernel(const DevSeg* __restrict__ s
     __shared__ int32_t s_shptr[BASIS_SHELLS + 1];
     (void)spline_lds;  // the launcher sized the dynamic LDS for the table
     const int tid = threadIdx.x;
+    const DevSys* table_of = nullptr;  // the system whose spline table is in LDS
     for (int64_t v_ = blockIdx.x; v_ < xcd_span(total); v_ += gridDim.x) {
         const int64_t bi = xcd_item(v_, total);
         if (bi >= total) continue;
@@ -187,9 +204,21 @@ __global__ __launch_bounds__(256) void basis_kernel(const DevSeg* __restrict__ s
         gp<const int32_t> shell_rad = gptr(S->shell_radial);
         gp<const double> rpar = gptr(S->radial_par);
         const bool staged = na <= BASIS_ATOMS && n_sh <= BASIS_SHELLS && n_sp <= BASIS_SHELLS;  // uniform
-        if (SPLINE_LDS) {
-            const int nsp = S->n_radial * (nk - 1) * 4;
+        // the table is staged once per workgroup and system (the grid is capped, so that a
+        // workgroup takes many items)
+        const bool restage = SPLINE_LDS && S != table_of;  // uniform
+        if (restage) {
+            const int nsp = S->n_radial * nk * 2;
             for (int i = tid; i < nsp; i += blockDim.x) lds_spline[i] = spl[i];
+            table_of = S;
+        }
+        if (STAGE) {
+            for (int i = tid; i < row1 - row0; i += blockDim.x) {
+                const int64_t p = u.point_begin + row0 + i;
+                s_pt[i][0] = gptr(S->px)[p];
+                s_pt[i][1] = gptr(S->py)[p];
+                s_pt[i][2] = gptr(S->pz)[p];
+            }
         }
         if (staged) {
             for (int ai = tid; ai < na; ai += blockDim.x) {
@@ -208,7 +237,7 @@ __global__ __launch_bounds__(256) void basis_kernel(const DevSeg* __restrict__ s
             }
             for (int k = tid; k <= n_sp; k += blockDim.x) s_shptr[k] = shell_ptr[k];
         }
-        if (SPLINE_LDS || staged) __syncthreads();
+        if (restage || staged || STAGE) __syncthreads();
         gp<T> __restrict__ out = gptr(static_cast<T*>(sg.phi) + u.out_offset);
         // EX = EXTRA_GRAD: 3 gradient values per basis value; EX = EXTRA_GGA_L: L = (w v / 2) phi +
         // (w a) . grad phi, one per basis value; EX = EXTRA_KS_L: L = (w v / 2) phi - (w / 4) lap phi
@@ -220,6 +249,8 @@ __global__ __launch_bounds__(256) void basis_kernel(const DevSeg* __restrict__ s
         const int64_t npairs = (int64_t)(row1 - row0) * na;
         const double tmax = (double)(nk - 1);
 
+        // Gradient and L values (EX != EXTRA_NONE): threads over (point, atom) pairs, each writing
+        // every value of its pair directly.
         auto pairs = [&](auto on_chip) {
             constexpr bool ST = decltype(on_chip)::value;
             for (int64_t q = tid; q < npairs; q += blockDim.x) {
@@ -261,9 +292,9 @@ __global__ __launch_bounds__(256) void basis_kernel(const DevSeg* __restrict__ s
                     uy = dy * ir;
                     uz = dz * ir;
                 }
+                double Y[16];
                 int lmax = 0;
                 for (int j = sh0; j < sh1; ++j) lmax = max(lmax, ST ? s_shell[j][0] : shell_l[j]);
-                double Y[16];
                 real_ylm(ux, uy, uz, lmax, Y);
                 const double lnr = r > 0.0 ? log(r) : 0.0;
                 for (int j = sh0; j < sh1; ++j) {
@@ -278,21 +309,23 @@ __global__ __launch_bounds__(256) void basis_kernel(const DevSeg* __restrict__ s
                         double t = r > rmin ? (lnr - lnmin) * idel : 0.0;
                         t = fmin(fmax(t, 0.0), tmax);
                         const int k = min((int)t, nk - 2);
-                        const double w = t - (double)k;
-                        const int64_t ci = ((int64_t)rr * (nk - 1) + k) * 4;
-                        double c0, c1, c2, c3;
+                        const double w = t - (double)k, v = 1.0 - w;
+                        // knots k and k + 1: (y_k, M_k / 6, y_{k+1}, M_{k+1} / 6), 32 contiguous bytes
+                        const int64_t ci = ((int64_t)rr * nk + k) * 2;
+                        double ya, pa, yb, pb;
                         if (SPLINE_LDS) {
-                            c0 = lds_spline[ci], c1 = lds_spline[ci + 1], c2 = lds_spline[ci + 2], c3 = lds_spline[ci + 3];
+                            ya = lds_spline[ci], pa = lds_spline[ci + 1], yb = lds_spline[ci + 2], pb = lds_spline[ci + 3];
                         } else {
                             gp<const double> c = spl + ci;
-                            c0 = c[0], c1 = c[1], c2 = c[2], c3 = c[3];
+                            ya = c[0], pa = c[1], yb = c[2], pb = c[3];
                         }
-                        R = c0 + w * (c1 + w * (c2 + w * c3));
+                        R = v * (ya + (v * v - 1.0) * pa) + w * (yb + (w * w - 1.0) * pb);
                         // dR/dr = dR/dw dt/dr with dt/dr = 1 / (r Delta); the clamped part r <= rmin is constant
-                        if (EX != EXTRA_NONE && r > rmin) dR = (c1 + w * (2.0 * c2 + 3.0 * c3 * w)) * idel / r;
+                        const double dRdw = (yb - ya) - (3.0 * v * v - 1.0) * pa + (3.0 * w * w - 1.0) * pb;
+                        if (EX != EXTRA_NONE && r > rmin) dR = dRdw * idel / r;
                         if (KS) {
-                            dS = c1 + w * (2.0 * c2 + 3.0 * c3 * w);  // dR/dt
-                            d2S = 2.0 * c2 + 6.0 * c3 * w;           // d2R/dt2
+                            dS = dRdw;                    // dR/dt
+                            d2S = 6.0 * (v * pa + w * pb);  // d2R/dt2
                         }
                     }
                     if (EX != EXTRA_NONE) {
@@ -334,33 +367,147 @@ __global__ __launch_bounds__(256) void basis_kernel(const DevSeg* __restrict__ s
                             }
                         }
                     }
+                    auto put = [&](auto deg) {
+                        constexpr int L = decltype(deg)::value;
+#pragma unroll
+                        for (int f = 0; f < 2 * L + 1; ++f) row[col + f] = T(R * Y[L * L + f]);
+                        col += 2 * L + 1;
+                    };
                     switch (l) {
-                    case 0:
-                        row[col] = T(R * Y[0]);
-                        col += 1;
-                        break;
-                    case 1:
-                        row[col] = T(R * Y[1]);
-                        row[col + 1] = T(R * Y[2]);
-                        row[col + 2] = T(R * Y[3]);
-                        col += 3;
-                        break;
-                    case 2:
-#pragma unroll
-                        for (int f = 0; f < 5; ++f) row[col + f] = T(R * Y[4 + f]);
-                        col += 5;
-                        break;
-                    default:
-#pragma unroll
-                        for (int f = 0; f < 7; ++f) row[col + f] = T(R * Y[9 + f]);
-                        col += 7;
-                        break;
+                    case 0: put(std::integral_constant<int, 0>{}); break;
+                    case 1: put(std::integral_constant<int, 1>{}); break;
+                    case 2: put(std::integral_constant<int, 2>{}); break;
+                    default: put(std::integral_constant<int, 3>{}); break;
                     }
                 }
             }
         };
-        if (staged) pairs(std::true_type{});
-        else pairs(std::false_type{});
+        // Plain values: a wave's 64 pairs are consecutive atoms of one or a few points, whose
+        // columns are consecutive in the row, so the values are staged in LDS, BASIS_WIN per pair
+        // at a time, and written as contiguous runs of the rows (a store per value and lane would
+        // touch a separate cache line per lane).
+        auto pairs_staged = [&](auto on_chip) {
+            constexpr bool ST = decltype(on_chip)::value;
+            constexpr int BW = BASIS_WIN, BWP = BASIS_WIN + 1;
+            const int lane = tid & 63, wave = tid >> 6;
+            double* win = &s_win[wave * 64 * BWP];
+            int32_t* pinfo = &s_pair[wave * 64 * 2];
+            for (int64_t qb = tid - lane; qb < npairs; qb += blockDim.x) {  // wave-uniform trip count
+                const int64_t q = qb + lane;
+                const bool valid = q < npairs;
+                const int ql = (int)(valid ? q : qb);  // lanes past the end redo the wave's first pair
+                const int pq = ql / na;
+                const int ai = ql - pq * na;
+                const int pl = row0 + pq;
+                const int atom = ST ? 0 : uat[ai];
+                const int col = ST ? s_aspc[ai][1] : ucol[ai];
+                const double ax = ST ? s_atom[ai][0] : axyz[4 * (int64_t)atom];
+                const double ay = ST ? s_atom[ai][1] : axyz[4 * (int64_t)atom + 1];
+                const double az = ST ? s_atom[ai][2] : axyz[4 * (int64_t)atom + 2];
+                const double arc2 = ST ? s_atom[ai][3] : axyz[4 * (int64_t)atom + 3];
+                const double dx = s_pt[pq][0] - ax;
+                const double dy = s_pt[pq][1] - ay;
+                const double dz = s_pt[pq][2] - az;
+                const double d2 = dist2_exact(dx, dy, dz);
+                const int sp = ST ? s_aspc[ai][0] : aspecies[atom];
+                const int sh0 = ST ? s_shptr[sp] : shell_ptr[sp];
+                const int sh1 = ST ? s_shptr[sp + 1] : shell_ptr[sp + 1];
+                const bool near = d2 < arc2;  // else every value of the pair is zero
+                const double r = near ? sqrt(d2) : 0.0;
+                double ux = 0.0, uy = 0.0, uz = 1.0;
+                if (r > 0.0) {
+                    const double ir = 1.0 / r;
+                    ux = dx * ir;
+                    uy = dy * ir;
+                    uz = dz * ir;
+                }
+                const double lnr = r > 0.0 ? log(r) : 0.0;
+                int nval = 0;
+                for (int j = sh0; j < sh1; ++j) nval += 2 * (ST ? s_shell[j][0] : shell_l[j]) + 1;
+                pinfo[2 * lane] = valid ? pl * u.ld + col : -1;
+                pinfo[2 * lane + 1] = nval;
+                int nmax = valid ? nval : 0;  // the wave's largest value count
+#pragma unroll
+                for (int o = 1; o < 64; o <<= 1) nmax = max(nmax, __shfl_xor(nmax, o));
+                for (int w0 = 0; w0 < nmax; w0 += BW) {
+                    // this pair's values w0 .. w0 + BW - 1 into its row of the window
+                    int off = 0;
+                    for (int j = sh0; j < sh1 && off < w0 + BW; ++j) {
+                        const int l = ST ? s_shell[j][0] : shell_l[j];
+                        const int nf = 2 * l + 1;
+                        if (off + nf > w0) {
+                            const int rr = ST ? s_shell[j][1] : shell_rad[j];
+                            const double rmin = ST ? s_par[j][0] : rpar[4 * rr];
+                            const double rc2 = ST ? s_par[j][1] : rpar[4 * rr + 1];
+                            const double idel = ST ? s_par[j][2] : rpar[4 * rr + 2];
+                            const double lnmin = ST ? s_par[j][3] : rpar[4 * rr + 3];
+                            double R = 0.0;
+                            if (near && d2 < rc2) {
+                                double t = r > rmin ? (lnr - lnmin) * idel : 0.0;
+                                t = fmin(fmax(t, 0.0), tmax);
+                                const int k = min((int)t, nk - 2);
+                                const double w = t - (double)k, v = 1.0 - w;
+                                const int64_t ci = ((int64_t)rr * nk + k) * 2;
+                                double ya, pa, yb, pb;
+                                if (SPLINE_LDS) {
+                                    ya = lds_spline[ci], pa = lds_spline[ci + 1], yb = lds_spline[ci + 2], pb = lds_spline[ci + 3];
+                                } else {
+                                    gp<const double> c = spl + ci;
+                                    ya = c[0], pa = c[1], yb = c[2], pb = c[3];
+                                }
+                                R = v * (ya + (v * v - 1.0) * pa) + w * (yb + (w * w - 1.0) * pb);
+                            }
+                            auto put = [&](auto deg) {
+                                constexpr int L = decltype(deg)::value;
+                                double Yl[2 * L + 1];
+                                ylm_l<L>(ux, uy, uz, Yl);
+#pragma unroll
+                                for (int f = 0; f < 2 * L + 1; ++f) {
+                                    const int slot = off + f - w0;
+                                    if (slot >= 0 && slot < BW) win[lane * BWP + slot] = R * Yl[f];
+                                }
+                            };
+                            switch (l) {
+                            case 0: put(std::integral_constant<int, 0>{}); break;
+                            case 1: put(std::integral_constant<int, 1>{}); break;
+                            case 2: put(std::integral_constant<int, 2>{}); break;
+                            default: put(std::integral_constant<int, 3>{}); break;
+                            }
+                        }
+                        off += nf;
+                    }
+                    // the wave's own LDS writes are performed before its later reads (in order)
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                    // element e = k 64 + lane of the 64 x BW window: pair e / BW, value e % BW;
+                    // the LDS reads of four elements are issued before their stores
+                    const int2* pinfo2 = reinterpret_cast<const int2*>(pinfo);
+#pragma unroll
+                    for (int kb = 0; kb < BW; kb += 4) {
+                        int2 pi[4];
+                        double val[4];
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            const int e = (kb + j) * 64 + lane;
+                            pi[j] = pinfo2[e / BW];
+                            val[j] = win[(e / BW) * BWP + e % BW];
+                        }
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            const int f = ((kb + j) * 64 + lane) % BW;
+                            if (pi[j].x >= 0 && w0 + f < pi[j].y) out[(int64_t)pi[j].x + w0 + f] = T(val[j]);
+                        }
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                }
+            }
+        };
+        if constexpr (STAGE) {
+            if (staged) pairs_staged(std::true_type{});
+            else pairs_staged(std::false_type{});
+        } else {
+            if (staged) pairs(std::true_type{});
+            else pairs(std::false_type{});
+        }
         const int pad = u.ld - u.m;
         if (pad > 0) {
             const int64_t ne = (int64_t)(row1 - row0) * pad;
@@ -393,6 +540,18 @@ hipError_t launch_basis(const DevSeg* segs_dev, int n_segs, int64_t n_units, int
     if (extra != EXTRA_NONE && extra != EXTRA_GRAD && extra != EXTRA_GGA_L && extra != EXTRA_KS_L)
         return hipErrorInvalidValue;
     const int64_t n_items = n_units * BASIS_SLICES;
+    // two workgroups per CU fit (LDS); a grid of that size takes many items per workgroup, which
+    // stages its spline table once
+    if (max_grid <= 0) {
+        static std::atomic<int> n_cu{0};
+        if (n_cu.load() == 0) {
+            int dev = 0, cu = 0;
+            if (hipGetDevice(&dev) == hipSuccess &&
+                hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cu > 0)
+                n_cu.store(cu);
+        }
+        max_grid = 2 * (int64_t)std::max(1, n_cu.load());
+    }
     const dim3 g(grid_for(n_items, max_grid)), b(256);
     const bool staged = spline_lds > 0;
     const size_t lds = (size_t)spline_lds * sizeof(double);
@@ -490,23 +649,31 @@ template <> struct Mma<float> {
     static __device__ inline int row(int lk, int r) { return 4 * lk + r; }
 };
 
-// Hamiltonian: per work item one 64x64 tile pair (I <= J) of a unit,
-//   H[I, J] += (w v Phi[:, I])^T Phi[:, J];
-// K loop over the unit's points in double-buffered chunks of 16 (register prefetch of the
-// next chunk while the MFMAs of the current one run); four waves, each a 32x32 quarter as
-// 2x2 MFMA blocks; FP64 atomics into the upper triangle of H.  T = FP32 accumulates a unit
-// (<= 256 points) in FP32 before the FP64 atomics.
-template <typename T>
-__global__ __launch_bounds__(256, 4) void h_kernel(const DevSeg* __restrict__ segs, int n_segs, int64_t total)
+// Hamiltonian, staged by direct global-to-LDS loads: per work item one 64x64 tile pair (I <= J)
+// of a unit, H[I, J] += (w v Phi[:, I])^T Phi[:, J].  K = the unit's points in chunks of KC
+// held in an S-stage ring in LDS: the loads of chunk c + S - 1 are issued (global_load_lds, 16
+// bytes per lane, no registers involved) while the MFMAs of chunk c run, so S - 1 chunks are in
+// flight.  w v of the unit's points is staged the same way once per item; the A operand is
+// scaled by it as it is read (loads of rows beyond the unit's last point are clamped into the
+// unit, and the w v of such rows is taken as zero).  On a diagonal pair (I == J) one tile
+// serves both operands.  Four waves, each a 32x32 quarter as 2x2 MFMA blocks; FP64 atomics
+// into the upper triangle of H.  The 16-byte loads need 16-byte aligned rows: every
+// basis-value block starts on a 64-value boundary of its buffer and ld is a multiple of 64.
+template <typename T, int KC, int S>
+__global__ __launch_bounds__(256) void h_kernel_dma(const DevSeg* __restrict__ segs, int n_segs, int64_t total)
 {
     typedef Mma<T> M;
-    constexpr int HK = KCHUNK;              // points per chunk
-    constexpr int HQ = HK * TILE / 256;     // values per thread per chunk and operand
-    __shared__ T As[2][HK][TILE + 2];
-    __shared__ T Bs[2][HK][TILE + 2];
+    constexpr int ROW_SLOTS = TILE * (int)sizeof(T) / 16;     // 16-byte slots per tile row
+    constexpr int ROWS_PER_LOAD = 64 / ROW_SLOTS;            // tile rows one wave load covers
+    constexpr int LOADS = KC / ROWS_PER_LOAD / 4;            // wave loads per operand and chunk
+    static_assert(LOADS >= 1 && KC % 4 == 0 && MAX_UNIT_POINTS % KC == 0, "chunk geometry");
+    __shared__ __align__(16) T st[S][2][KC][TILE];           // [stage][operand A, B][point][column]
+    __shared__ double wvs[MAX_UNIT_POINTS];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = wave >> 1, wc = wave & 1;
     const int lr = lane & 15, lk = lane >> 4;
+    // this lane's slot of every wave load: tile row (within the load's rows) and 16-byte column slot
+    const int slot_row = lane / ROW_SLOTS, slot_col = (lane % ROW_SLOTS) * (16 / (int)sizeof(T));
     for (int64_t v_ = blockIdx.x; v_ < xcd_span(total); v_ += gridDim.x) {
         const int64_t b = xcd_item(v_, total);
         if (b >= total) continue;
@@ -514,38 +681,65 @@ __global__ __launch_bounds__(256, 4) void h_kernel(const DevSeg* __restrict__ se
         const DevSeg& sg = segs[s];
         const HItem it = static_cast<const HItem*>(sg.items)[sg.item_begin + (b - sg.item_prefix)];
         const DevUnit u = sg.units[it.unit];
-        gp<const T> __restrict__ phi = gptr(static_cast<const T*>(sg.phi) + u.out_offset);
-        gp<const double> __restrict__ wv = gptr(sg.wv + u.point_begin);
         const int np = u.n_points, ld = u.ld;
-        const int I0 = it.ti * TILE, J0 = it.tj * TILE;
-        const int n_chunks = (np + HK - 1) / HK;
-
         if (np <= 0) continue;
-        // Loads are issued unconditionally (rows clamped into the unit) and only consumed at
-        // the stash after the next chunk's MFMAs, so that they stay in flight meanwhile.
-        T ra[HQ], rb[HQ];
-        double rw[HQ];
-        auto fetch = [&](int c) {
+        const T* phi = static_cast<const T*>(sg.phi) + u.out_offset;
+        const int I0 = it.ti * TILE, J0 = it.tj * TILE;
+        const bool diag = it.ti == it.tj;
+        const int n_chunks = (np + KC - 1) / KC;
+        const int per_chunk = diag ? LOADS : 2 * LOADS;  // wave loads per chunk (wave-uniform)
+
+        // every wave must be done reading the previous item's stages and w v before they are
+        // refilled (its loads into them have all completed; its atomics need not)
+        __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+        // w v of the unit's points into wvs, 32 per wave load (two 4-byte halves per value), point
+        // indices clamped into the unit; rows at and beyond np are masked where they are used
+        {
+            const double* wv = sg.wv + u.point_begin;
+            const int nq = (n_chunks * KC + 31) / 32;
+            for (int q = wave; q < nq; q += 4) {
+                const int d = min(32 * q + (lane >> 1), np - 1);
+                const char* src = reinterpret_cast<const char*>(wv + d) + 4 * (lane & 1);
+                __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
+                                                 (__attribute__((address_space(3))) void*)&wvs[32 * q], 4, 0, 0);
+            }
+        }
+        auto issue = [&](int c) {
+            const int stg = c % S;
 #pragma unroll
-            for (int q = 0; q < HQ; ++q) {
-                const int e = tid + 256 * q;
-                const int pc = min(c * HK + (e >> 6), np - 1), col = e & 63;
-                gp<const T> rowp = phi + (int64_t)pc * ld;
-                ra[q] = rowp[I0 + col];
-                rb[q] = rowp[J0 + col];
-                rw[q] = wv[pc];
+            for (int op = 0; op < 2; ++op) {
+                if (op == 1 && diag) break;
+                const int col0 = op == 0 ? I0 : J0;
+#pragma unroll
+                for (int q = 0; q < LOADS; ++q) {
+                    const int r0 = (wave * LOADS + q) * ROWS_PER_LOAD;  // first tile row of this load
+                    const int p = min(c * KC + r0 + slot_row, np - 1);
+                    const T* src = phi + (int64_t)p * ld + col0 + slot_col;
+                    __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
+                                                     (__attribute__((address_space(3))) void*)&st[stg][op][r0][0],
+                                                     16, 0, 0);
+                }
             }
         };
-        auto stash = [&](int c, int buf) {
-#pragma unroll
-            for (int q = 0; q < HQ; ++q) {
-                const int e = tid + 256 * q;
-                const bool ok = c * HK + (e >> 6) < np;
-                As[buf][e >> 6][e & 63] = ok ? T((double)ra[q] * rw[q]) : T(0);
-                Bs[buf][e >> 6][e & 63] = ok ? rb[q] : T(0);
+        // wait until at most `later` chunks' loads of this wave are outstanding (vmcnt counts wave
+        // loads in issue order), and for the LDS reads of the last chunk, then barrier
+        auto sync_chunk = [&](int later) {
+            const int n = __builtin_amdgcn_readfirstlane(later * per_chunk);  // at most (S - 2) * 2 * LOADS
+            switch (n) {
+#define NAO_VMWAIT(N) \
+    case N: __builtin_amdgcn_s_waitcnt(((N) & 0xF) | (((N) >> 4) << 14) | (0x7 << 4)); break;
+                NAO_VMWAIT(0) NAO_VMWAIT(1) NAO_VMWAIT(2) NAO_VMWAIT(3) NAO_VMWAIT(4) NAO_VMWAIT(5)
+                NAO_VMWAIT(6) NAO_VMWAIT(7) NAO_VMWAIT(8) NAO_VMWAIT(9) NAO_VMWAIT(10) NAO_VMWAIT(11)
+                NAO_VMWAIT(12) NAO_VMWAIT(13) NAO_VMWAIT(14) NAO_VMWAIT(15) NAO_VMWAIT(16)
+#undef NAO_VMWAIT
+            default: __builtin_amdgcn_s_waitcnt(0x7 << 4); break;  // vmcnt(0), lgkmcnt(0)
             }
+            __builtin_amdgcn_s_barrier();
+            asm volatile("" ::: "memory");
         };
-        // global indices of this lane's output rows and columns, needed only after the K loop
+
         gp<const int32_t> __restrict__ fn = gptr(sg.unit_fn + u.fn_begin);
         int32_t gI[2][4], gJ[2];
 #pragma unroll
@@ -554,45 +748,36 @@ __global__ __launch_bounds__(256, 4) void h_kernel(const DevSeg* __restrict__ se
             for (int r = 0; r < 4; ++r) gI[ib][r] = fn[min(I0 + wr * 32 + ib * 16 + M::row(lk, r), u.m - 1)];
             gJ[ib] = fn[min(J0 + wc * 32 + ib * 16 + lr, u.m - 1)];
         }
-
         typename M::acc_t acc[2][2];
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
             for (int j = 0; j < 2; ++j) acc[i][j] = M::zero();
-        // On a diagonal tile pair the wave of the strictly lower quarter only stages data.
-        auto k_loop = [&](auto with_mfma) {
-            fetch(0);
-            stash(0, 0);
-            __syncthreads();
-            for (int c = 0; c < n_chunks; ++c) {
-                const int buf = c & 1;
-                if (c + 1 < n_chunks) fetch(c + 1);
-                if (decltype(with_mfma)::value) {
-#pragma unroll
-                    for (int kk = 0; kk < HK / 4; ++kk) {
-                        const int kr = kk * 4 + lk;
-                        const T a0 = As[buf][kr][wr * 32 + lr];
-                        const T a1 = As[buf][kr][wr * 32 + 16 + lr];
-                        const T b0 = Bs[buf][kr][wc * 32 + lr];
-                        const T b1 = Bs[buf][kr][wc * 32 + 16 + lr];
-                        acc[0][0] = M::op(a0, b0, acc[0][0]);
-                        acc[0][1] = M::op(a0, b1, acc[0][1]);
-                        acc[1][0] = M::op(a1, b0, acc[1][0]);
-                        acc[1][1] = M::op(a1, b1, acc[1][1]);
-                    }
-                }
-                if (c + 1 < n_chunks) stash(c + 1, buf ^ 1);
-                __syncthreads();
-            }
-        };
-        const bool diag = it.ti == it.tj;
-        if (diag && wr > wc) {
-            k_loop(std::false_type{});
-            continue;
-        }
-        k_loop(std::true_type{});
+        const bool compute = !(diag && wr > wc);  // the strictly lower quarter of a diagonal pair
+        const int ob = diag ? 0 : 1;              // operand B's slot in the stages
 
+        for (int c = 0; c < S - 1 && c < n_chunks; ++c) issue(c);
+        for (int c = 0; c < n_chunks; ++c) {
+            sync_chunk(min(S - 2, n_chunks - 1 - c));
+            if (c + S - 1 < n_chunks) issue(c + S - 1);
+            if (compute) {
+                const int stg = c % S;
+#pragma unroll
+                for (int kk = 0; kk < KC / 4; ++kk) {
+                    const int kr = kk * 4 + lk;
+                    const double w = c * KC + kr < np ? wvs[c * KC + kr] : 0.0;
+                    const T a0 = T((double)st[stg][0][kr][wr * 32 + lr] * w);
+                    const T a1 = T((double)st[stg][0][kr][wr * 32 + 16 + lr] * w);
+                    const T b0 = st[stg][ob][kr][wc * 32 + lr];
+                    const T b1 = st[stg][ob][kr][wc * 32 + 16 + lr];
+                    acc[0][0] = M::op(a0, b0, acc[0][0]);
+                    acc[0][1] = M::op(a0, b1, acc[0][1]);
+                    acc[1][0] = M::op(a1, b0, acc[1][0]);
+                    acc[1][1] = M::op(a1, b1, acc[1][1]);
+                }
+            }
+        }
+        if (!compute) continue;
         gp<double> __restrict__ H = gptr(sg.H);
         const int64_t ldh = sg.ld;
 #pragma unroll
@@ -1436,8 +1621,8 @@ hipError_t launch_h(Mode mode, const DevSeg* segs_dev, int n_segs, int64_t n_ite
     if (n_items > 0x7ffffff0) return hipErrorInvalidValue;
     const dim3 g(grid_for(n_items, max_grid)), b(256);
     switch (mode) {
-    case MODE_FP64: hipLaunchKernelGGL(h_kernel<double>, g, b, 0, st, segs_dev, n_segs, n_items); break;
-    case MODE_FP32: hipLaunchKernelGGL(h_kernel<float>, g, b, 0, st, segs_dev, n_segs, n_items); break;
+    case MODE_FP64: hipLaunchKernelGGL((h_kernel_dma<double, 16, 3>), g, b, 0, st, segs_dev, n_segs, n_items); break;
+    case MODE_FP32: hipLaunchKernelGGL((h_kernel_dma<float, 16, 3>), g, b, 0, st, segs_dev, n_segs, n_items); break;
     case MODE_BF16X3: hipLaunchKernelGGL(h_kernel_bf16<2>, g, b, 0, st, segs_dev, n_segs, n_items); break;
     case MODE_BF16X6: hipLaunchKernelGGL(h_kernel_bf16<3>, g, b, 0, st, segs_dev, n_segs, n_items); break;
     default: return hipErrorInvalidValue;

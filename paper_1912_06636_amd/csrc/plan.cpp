@@ -368,10 +368,10 @@ void expand_lists(const HostBasis& b, const std::vector<int64_t>& atom_ptr,
 // ------------------------------------------------------------------------------------------
 // splines
 
-std::vector<double> spline_coefficients(const HostBasis& b)
+std::vector<double> spline_knots(const HostBasis& b)
 {
     const int N = b.n_knots;
-    std::vector<double> out((size_t)b.n_radial * (N - 1) * 4);
+    std::vector<double> out((size_t)b.n_radial * N * 2);
     std::vector<double> M(N), diag(N), rhs(N);
     for (int32_t r = 0; r < b.n_radial; ++r) {
         const double* y = b.samples.data() + (size_t)r * N;
@@ -389,13 +389,11 @@ std::vector<double> spline_coefficients(const HostBasis& b)
         M[N - 1] = 0.0;
         M[N - 2] = rhs[N - 2] / diag[N - 2];
         for (int k = N - 3; k >= 1; --k) M[k] = (rhs[k] - M[k + 1]) / diag[k];
-        for (int k = 0; k < N - 1; ++k) {
-            double* c = out.data() + ((size_t)r * (N - 1) + k) * 4;
-            // (1-u) y_k + u y_{k+1} + (((1-u)^3 - (1-u)) M_k + (u^3 - u) M_{k+1}) / 6 in powers of u
-            c[0] = y[k];
-            c[1] = (y[k + 1] - y[k]) - (2.0 * M[k] + M[k + 1]) / 6.0;
-            c[2] = 0.5 * M[k];
-            c[3] = (M[k + 1] - M[k]) / 6.0;
+        // per knot (y_k, M_k / 6): on [k, k+1], with v = 1 - u,
+        //   R = v (y_k + (v^2 - 1) M_k / 6) + u (y_{k+1} + (u^2 - 1) M_{k+1} / 6)
+        for (int k = 0; k < N; ++k) {
+            out[((size_t)r * N + k) * 2] = y[k];
+            out[((size_t)r * N + k) * 2 + 1] = M[k] / 6.0;
         }
     }
     return out;

@@ -53,9 +53,10 @@ void expand_lists(const HostBasis& b, const std::vector<int64_t>& atom_ptr,
                   const std::vector<int32_t>& atoms, std::vector<int64_t>& basis_ptr,
                   std::vector<int32_t>& basis_idx);
 
-// Natural cubic spline in the unit-spaced coordinate t, as per-interval polynomial
-// coefficients: R(k + u) = c0 + u (c1 + u (c2 + u c3)), layout [n_radial][n_knots-1][4].
-std::vector<double> spline_coefficients(const HostBasis& b);
+// Natural cubic spline in the unit-spaced coordinate t, stored per knot as (y_k, M_k / 6) with
+// M the second derivative: layout [n_radial][n_knots][2].  On [k, k+1], u = t - k, v = 1 - u:
+// R = v (y_k + (v^2 - 1) M_k / 6) + u (y_{k+1} + (u^2 - 1) M_{k+1} / 6).
+std::vector<double> spline_knots(const HostBasis& b);
 
 // An execution unit: a run of batch-ordered points with the union of their lists.
 struct Unit {

@@ -1090,7 +1090,7 @@ static nao_status setup_system(nao_system s, const double* xyz, const double* w)
         rpar[4 * r + 2] = (double)(B.n_knots - 1) / std::log(B.rcut[r] / B.rmin[r]);
         rpar[4 * r + 3] = std::log(B.rmin[r]);
     }
-    std::vector<double> spl = spline_coefficients(B);
+    std::vector<double> spl = spline_knots(B);
     s->spline_lds = spl.size() <= (size_t)MAX_SPLINE_LDS ? (int)spl.size() : 0;
     nao_status st;
 #define UP(arr, vec) \

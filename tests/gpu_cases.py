@@ -52,7 +52,7 @@ def case(name):
         w = dict(basis=basis, xyz=X, w=wt, v=v, D=0.5 * (D + D.T), C=C, max_batch=64, n_basis=nb)
     elif name == "two_species_8":
         # two species with 8 radial functions each (the shape of a two-element slab basis): a
-        # 16 x 199 x 4 spline table, more than the basis kernel stages on chip
+        # 16 x 200 x 2 knot table, which the basis kernel stages on chip
         xyz = g.geometry_sc_first_n(6, 2.3, 0.1, g.rng_for(7, 8, 0))
         basis = g.make_basis(xyz, np.array([0, 1, 0, 1, 0, 1], np.int32),
                              [(0, 0, 1, 1, 1, 2, 2, 3), (0, 0, 1, 1, 2, 2, 3, 3)], [5.0, 4.0], 7, 8)

@@ -211,17 +211,22 @@ void check_plan(int seed, int n_atoms, int64_t n, double box, bool coincident)
                 CHECK(bu.size() == bp.size() - 1);
             }
         }
-    // spline coefficients reproduce the knots
-    const std::vector<double> c = spline_coefficients(hb);
+    // the knot table holds the samples and the natural spline's M_k / 6: M_0 = M_{N-1} = 0 and
+    // M_{k-1} + 4 M_k + M_{k+1} = 6 (y_{k-1} - 2 y_k + y_{k+1}) at every interior knot
+    const std::vector<double> c = spline_knots(hb);
     const int nk = hb.n_knots;
-    CHECK((int)c.size() == hb.n_radial * (nk - 1) * 4);
-    for (int r = 0; r < hb.n_radial; ++r)
-        for (int k = 0; k + 1 < nk; ++k) {
-            const double* q = &c[((size_t)r * (nk - 1) + k) * 4];
-            CHECK(std::fabs(q[0] - hb.samples[(size_t)r * nk + k]) <= 1e-12 * (1 + std::fabs(q[0])));
-            const double end = q[0] + q[1] + q[2] + q[3];
-            CHECK(std::fabs(end - hb.samples[(size_t)r * nk + k + 1]) <= 1e-9 * (1 + std::fabs(end)));
+    CHECK((int)c.size() == hb.n_radial * nk * 2);
+    for (int r = 0; r < hb.n_radial; ++r) {
+        const double* q = &c[(size_t)r * nk * 2];
+        const double* y = &hb.samples[(size_t)r * nk];
+        CHECK(q[1] == 0.0 && q[2 * (nk - 1) + 1] == 0.0);
+        for (int k = 0; k < nk; ++k) CHECK(q[2 * k] == y[k]);
+        for (int k = 1; k + 1 < nk; ++k) {
+            const double lhs = 6.0 * (q[2 * k - 1] + 4.0 * q[2 * k + 1] + q[2 * k + 3]);
+            const double rhs = 6.0 * (y[k - 1] - 2.0 * y[k] + y[k + 1]);
+            CHECK(std::fabs(lhs - rhs) <= 1e-9 * (1 + std::fabs(rhs)));
         }
+    }
 }
 
 int main()

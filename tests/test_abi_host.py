@@ -154,22 +154,22 @@ def test_unknown_batcher_is_rejected():
 
 def test_off_chip_cases_select_their_branches():
     """The inputs of tests/test_gpu_basis_fallback.py take the branches they are meant to test:
-    a spline table larger than the 8,192 doubles the basis kernel stages in LDS, a batch (and so
-    a unit) with more than the 256 atoms it stages, a system with more than the 128 shells it
-    stages."""
+    a spline table larger than the 8,192 doubles the basis kernel stages in LDS (and the
+    two-species, 8-radial basis of a two-element slab within it), a batch (and so a unit) with
+    more than the 192 atoms it stages, a system with more than the 128 shells it stages."""
     from paper_1912_06636_amd import nao
     from tests.gpu_cases import case
     for name in ("two_species_8", "dense_cluster", "many_species"):
         w, B, ref = case(name)
         b = w["basis"]
-        table = len(b["radial_rmin"]) * (b["n_knots"] - 1) * 4
+        table = len(b["radial_rmin"]) * b["n_knots"] * 2  # (y_k, M_k / 6) per knot
         n_shells = int(b["species_shell_ptr"][-1])
         perm, bp, lp, li = nao.plan_create(b, w["xyz"], w["max_batch"])
         owner = g.basis_atom_index(b)
         most_atoms = max(len(set(owner[li[lp[k]:lp[k + 1]]].tolist())) for k in range(len(lp) - 1))
         if name == "two_species_8":
-            assert table > 8192
+            assert table <= 8192 and len(b["radial_rmin"]) == 16
         if name == "dense_cluster":
-            assert most_atoms > 256
+            assert most_atoms > 192
         if name == "many_species":
             assert n_shells > 128 and table > 8192

@@ -1,9 +1,9 @@
 """The basis kernel's off-chip branches against the oracle: a spline table larger than the kernel
-stages in LDS (two species with 8 radial functions each, as in a two-element slab; also the
-135-shell case), units with more atoms than it stages (a 343-atom dense cluster) and systems
-with more shells than it stages (nine species of 15 shells).  Every operation that evaluates
-basis values is checked: basis values, H and n in FP64 and FP32, the density gradient, the
-Kohn-Sham Hamiltonian with a field, and the many-structure launch."""
+stages in LDS and more shells than it stages (nine species of 15 shells: 135 radial functions),
+units with more atoms than it stages (a 343-atom dense cluster); beside them the two-species basis
+with 8 radial functions each of a two-element slab, whose table is staged on chip.  Every
+operation that evaluates basis values is checked: basis values, H and n in FP64 and FP32, the
+density gradient, the Kohn-Sham Hamiltonian with a field, and the many-structure launch."""
 import functools
 import sys
 
@@ -17,7 +17,7 @@ pytestmark = pytest.mark.gpu
 
 CASES = ["two_species_8", "dense_cluster", "many_species"]
 SPLINE_LDS_DOUBLES = 8192   # table size the basis kernel stages in LDS
-STAGED_ATOMS, STAGED_SHELLS = 256, 128
+STAGED_ATOMS, STAGED_SHELLS = 192, 128
 
 
 def say(*a):
@@ -92,7 +92,7 @@ def test_gradient_and_ks_hamiltonian(nao, ctx, name):
 
 
 def test_many_structure_launch(nao, ctx):
-    """nao_run_many over the three cases at once (no spline staging since the tables do not fit)."""
+    """nao_run_many over the three cases at once (no spline staging: one table does not fit)."""
     import torch
     dev = torch.device("cuda:0")
     systems, outs, work = [], [], []
