@@ -246,17 +246,19 @@ def density_gradient_at(basis, pts, D) -> np.ndarray:
     return out
 
 
-def pulay_forces(basis, xyz, w, v, D, Q, chunks=None) -> np.ndarray:
-    """Local Pulay forces F_A [n_atoms][3] (the density-only part of the Pulay force that
-    follows eq. forces), with h_KS acting as multiplication by the local potential v:
-        F_A = -2 sum_ij sum_p w_p [grad_A phi_i](r_p) (n_ij v_p - q_ij) phi_j(r_p),
-    n the density matrix D and q the energy-weighted density matrix Q (eq. E_Weighted_DM),
-    both symmetric, upper triangles read.  grad_A phi_i = -grad phi_i for the functions i
-    centred on A and 0 for all others, so with M = (w v) (Phi D) - w (Phi Q) per point,
+def pulay_forces(basis, xyz, w, v, D, Q, chunks=None, kinetic=True) -> np.ndarray:
+    """Local Pulay forces F_A [n_atoms][3], the density-only part of the Pulay force that follows
+    eq. forces:
+        F_A = -2 sum_ij sum_p w_p [grad_A phi_i](r_p) (n_ij [h_KS phi_j](r_p) - q_ij phi_j(r_p)),
+    h_KS = t + v with t = -1/2 lap the (non-relativistic) kinetic operator and v the local
+    potential (kinetic=False: v alone), n the density matrix D and q the energy-weighted density
+    matrix Q (eq. E_Weighted_DM), both symmetric, upper triangles read.  grad_A phi_i = -grad
+    phi_i for the functions i centred on A and 0 for all others, so with, per point,
+        M = w ((v Phi - lap Phi / 2) D - Phi Q),
         f_i = sum_p grad phi_i(r_p) M_pi,   F_A = 2 sum_{i on A} f_i."""
     xyz = np.asarray(xyz, dtype=np.float64).reshape(-1, 3)
     w = np.asarray(w, dtype=np.float64)
-    wv = w * np.asarray(v, dtype=np.float64)
+    v = np.asarray(v, dtype=np.float64)
     Ds = symmetric_from_upper(D)
     Qs = symmetric_from_upper(Q)
     f = np.zeros((basis.n_basis, 3))
@@ -267,7 +269,10 @@ def pulay_forces(basis, xyz, w, v, D, Q, chunks=None) -> np.ndarray:
         fns = basis.functions_of(atoms)
         Phi = basis.phi(xyz[idx], atoms)
         G = basis.grad_phi(xyz[idx], atoms)
-        M = wv[idx][:, None] * (Phi @ Ds[np.ix_(fns, fns)]) - w[idx][:, None] * (Phi @ Qs[np.ix_(fns, fns)])
+        hPhi = v[idx][:, None] * Phi  # h_KS phi_j at the points
+        if kinetic:
+            hPhi = hPhi - 0.5 * basis.lap_phi(xyz[idx], atoms)
+        M = w[idx][:, None] * (hPhi @ Ds[np.ix_(fns, fns)] - Phi @ Qs[np.ix_(fns, fns)])
         for k in range(3):
             f[fns, k] += (G[:, :, k] * M).sum(axis=0)
     F = np.zeros((len(basis.atom_xyz), 3))
@@ -276,13 +281,13 @@ def pulay_forces(basis, xyz, w, v, D, Q, chunks=None) -> np.ndarray:
     return F
 
 
-def pulay_forces_at(basis, xyz, w, v, D, Q, atoms) -> np.ndarray:
+def pulay_forces_at(basis, xyz, w, v, D, Q, atoms, kinetic=True) -> np.ndarray:
     """pulay_forces for selected atoms only: the points inside atom A's cutoff sphere (the
     only ones where grad_A phi is not zero), against every function reaching them (sampled
     checks at full size)."""
     xyz = np.asarray(xyz, dtype=np.float64).reshape(-1, 3)
     w = np.asarray(w, dtype=np.float64)
-    wv = w * np.asarray(v, dtype=np.float64)
+    v = np.asarray(v, dtype=np.float64)
     Ds = symmetric_from_upper(D)
     Qs = symmetric_from_upper(Q)
     out = np.zeros((len(atoms), 3))
@@ -299,9 +304,11 @@ def pulay_forces_at(basis, xyz, w, v, D, Q, atoms) -> np.ndarray:
             rel = relevant_atoms_of_points(xyz[idx], basis.atom_xyz, basis.atom_rcut)
             fns = basis.functions_of(rel)
             Phi = basis.phi(xyz[idx], rel)
+            hPhi = v[idx][:, None] * Phi
+            if kinetic:
+                hPhi = hPhi - 0.5 * basis.lap_phi(xyz[idx], rel)
             GA = basis.grad_phi_atom(xyz[idx], A)
-            M = (wv[idx][:, None] * (Phi @ Ds[np.ix_(fns, fa)])
-                 - w[idx][:, None] * (Phi @ Qs[np.ix_(fns, fa)]))
+            M = w[idx][:, None] * (hPhi @ Ds[np.ix_(fns, fa)] - Phi @ Qs[np.ix_(fns, fa)])
             for c in range(3):
                 out[k, c] += 2.0 * float((GA[:, :, c] * M).sum())
     return out
