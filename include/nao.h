@@ -326,18 +326,18 @@ nao_status nao_update_density_gradient(nao_system sys, const double* D, nao_mems
                                        nao_memspace out_space);
 
 /* ---------------------------------------------------------------------------------------
- * Local Pulay forces (the density-only Pulay term that follows eq. forces) with h_KS acting as
- * multiplication by the local potential v:
- *   F_A = -2 sum_ij sum_p w_p [grad_A phi_i](r_p) (D_ij v_p - Q_ij) phi_j(r_p),
+ * Local Pulay forces (the density-only Pulay term that follows eq. forces), with h_KS = t + v,
+ * t = -lap / 2 the non-relativistic kinetic operator and v the local potential:
+ *   F_A = -2 sum_ij sum_p w_p [grad_A phi_i](r_p) (D_ij [h_KS phi_j](r_p) - Q_ij phi_j(r_p)),
  * D the density matrix and Q the energy-weighted density matrix (eq. E_Weighted_DM), with
  * grad_A phi_i = -grad phi_i for the functions centred on atom A and 0 for the others.  Batch
- * by batch: M = diag(w v) Phi D_b - diag(w) Phi Q_b over the batch's whole list,
- * f_i += sum_p grad phi_pi M_pi, then F_A = 2 sum_{i on A} f_i.  grad phi as for
- * nao_update_density_gradient.  D and Q [N_b][N_b] row-major, symmetric, only their upper
- * triangles read; v [n_points] in caller point order; all three in in_space.
- * F [n_atoms][3] in F_space.  precision: NAO_FP64 or NAO_FP32 (other values give
- * NAO_ERR_INVALID_ARG).  Needs device scratch for the gradients of one block of basis values
- * (three times the basis scratch).
+ * by batch: M = diag(w) (diag(v) Phi - lap Phi / 2) D_b - diag(w) Phi Q_b over the batch's
+ * whole list, f_i += sum_p grad phi_pi M_pi, then F_A = 2 sum_{i on A} f_i.  grad phi as for
+ * nao_update_density_gradient, lap phi as for nao_integrate_h_ks.  D and Q [N_b][N_b]
+ * row-major, symmetric, only their upper triangles read; v [n_points] in caller point order;
+ * all three in in_space.  F [n_atoms][3] in F_space.  precision: NAO_FP64 or NAO_FP32 (other
+ * values give NAO_ERR_INVALID_ARG).  Needs device scratch for the gradients and Laplacians of
+ * one block of basis values (four times the basis scratch).
  * ------------------------------------------------------------------------------------- */
 nao_status nao_pulay_forces(nao_system sys, const double* D, const double* Q, const double* v,
                             nao_memspace in_space, nao_precision precision, double* F,

@@ -101,8 +101,10 @@ enum Mode { MODE_FP64 = 0, MODE_FP32 = 1, MODE_BF16X3 = 2, MODE_BF16X6 = 3 };
 // cover the largest table of the systems in the segment list.
 // extra: also write, to the segments' gphi, the gradient of every basis value (EXTRA_GRAD, 3 per
 // value), L = (w v / 2) phi + (w a) . grad phi (EXTRA_GGA_L, 1 per value; needs wv and wa) or
-// L = (w v / 2) phi - (w / 4) lap phi [+ (w a) . grad phi when wa is set] (EXTRA_KS_L, 1 per value).
-enum BasisExtra { EXTRA_NONE = 0, EXTRA_GRAD = 1, EXTRA_GGA_L = 2, EXTRA_KS_L = 3 };
+// L = (w v / 2) phi - (w / 4) lap phi [+ (w a) . grad phi when wa is set] (EXTRA_KS_L, 1 per value),
+// or the gradient and w h_KS phi = (w v) phi - (w / 2) lap phi (EXTRA_GRAD_H, 4 per value: x, y, z,
+// w h_KS phi; needs wv).
+enum BasisExtra { EXTRA_NONE = 0, EXTRA_GRAD = 1, EXTRA_GGA_L = 2, EXTRA_KS_L = 3, EXTRA_GRAD_H = 4 };
 hipError_t launch_basis(const DevSeg* segs_dev, int n_segs, int64_t n_units, int spline_lds, bool fp32_out,
                         hipStream_t st, int64_t max_grid = 0, int extra = EXTRA_NONE);
 // h_tile: 64, or 128 for the wide FP64/FP32 kernels (items then index 128-wide tiles).
@@ -117,8 +119,8 @@ hipError_t launch_n_grad(Mode mode, const DevSeg* segs_dev, int n_segs, int64_t 
 // 64-wide tile pairs I <= J, L from the basis launch with EXTRA_GGA_L.
 hipError_t launch_h_gga(Mode mode, const DevSeg* segs_dev, int n_segs, int64_t n_items, hipStream_t st);
 // Local Pulay forces (FP64 or FP32 modes), density items walked over the whole list twice:
-// fb[j] += sum_p grad phi_pj [(w v)_p (Phi D)_pj - w_p (Phi Q)_pj]; gphi from the basis launch
-// with EXTRA_GRAD, wv batch-ordered w*v.
+// fb[j] += sum_p grad phi_pj [((w v Phi - w lap Phi / 2) D)_pj - w_p (Phi Q)_pj]; gphi from the
+// basis launch with EXTRA_GRAD_H, wv batch-ordered w*v.
 hipError_t launch_n_force(Mode mode, const DevSeg* segs_dev, int n_segs, int64_t n_items, hipStream_t st);
 // F[a] = 2 sum over the functions i of atom a (atom_first[a] <= i < atom_first[a + 1]) of fb[i].
 hipError_t launch_force_atoms(const double* fb, const int64_t* atom_first, int64_t n_atoms, double* F,

@@ -242,9 +242,12 @@ __global__ __launch_bounds__(256, 2) void basis_kernel(const DevSeg* __restrict_
         // EX = EXTRA_GRAD: 3 gradient values per basis value; EX = EXTRA_GGA_L: L = (w v / 2) phi +
         // (w a) . grad phi, one per basis value; EX = EXTRA_KS_L: L = (w v / 2) phi - (w / 4) lap phi
         // (+ (w a) . grad phi when the segment has a field); same element order as the basis values
-        constexpr bool GRAD = EX == EXTRA_GRAD, GGA = EX == EXTRA_GGA_L, KS = EX == EXTRA_KS_L;
+        // EX = EXTRA_GRAD_H: the 3 gradient values and w h_KS phi = (w v) phi - (w / 2) lap phi, 4 per
+        // basis value
+        constexpr bool LAPL = EX == EXTRA_GRAD_H;
+        constexpr bool GRAD = EX == EXTRA_GRAD || LAPL, GGA = EX == EXTRA_GGA_L, KS = EX == EXTRA_KS_L;
         const bool field = GGA || (KS && sg.wa != nullptr);  // uniform
-        constexpr int XW = GRAD ? 3 : 1;  // extra values per basis value
+        constexpr int XW = GRAD ? (LAPL ? 4 : 3) : 1;  // extra values per basis value
         gp<T> __restrict__ gout = EX != EXTRA_NONE ? gptr(static_cast<T*>(sg.gphi) + XW * u.out_offset) : nullptr;
         const int64_t npairs = (int64_t)(row1 - row0) * na;
         const double tmax = (double)(nk - 1);
@@ -323,7 +326,7 @@ __global__ __launch_bounds__(256, 2) void basis_kernel(const DevSeg* __restrict_
                         // dR/dr = dR/dw dt/dr with dt/dr = 1 / (r Delta); the clamped part r <= rmin is constant
                         const double dRdw = (yb - ya) - (3.0 * v * v - 1.0) * pa + (3.0 * w * w - 1.0) * pb;
                         if (EX != EXTRA_NONE && r > rmin) dR = dRdw * idel / r;
-                        if (KS) {
+                        if (KS || LAPL) {
                             dS = dRdw;                    // dR/dt
                             d2S = 6.0 * (v * pa + w * pb);  // d2R/dt2
                         }
@@ -341,9 +344,12 @@ __global__ __launch_bounds__(256, 2) void basis_kernel(const DevSeg* __restrict_
                         }
                         // lap phi = (S''/Delta^2 + S'/Delta - l(l+1) S) Y / r^2 in the spline variable
                         double lap = 0.0;
-                        if (KS) {
-                            qw = 0.25 * gptr(S->pw)[p];
+                        if (KS || LAPL)
                             lap = live ? ((d2S * idel + dS) * idel - (double)(l * (l + 1)) * R) * ir * ir : 0.0;
+                        if (KS) qw = 0.25 * gptr(S->pw)[p];
+                        if (LAPL) {
+                            hwv = gptr(sg.wv)[p];
+                            qw = 0.5 * gptr(S->pw)[p];
                         }
                         for (int f = 0; f < 2 * l + 1; ++f) {
                             const int lm = l * l + f;
@@ -358,10 +364,11 @@ __global__ __launch_bounds__(256, 2) void basis_kernel(const DevSeg* __restrict_
                                 g2 = live ? dR * uz * yv + R * ir * (gv[2] - uz * ug) : 0.0;
                             }
                             if (GRAD) {
-                                gp<T> dst = grow + 3 * (int64_t)(col + f);
+                                gp<T> dst = grow + XW * (int64_t)(col + f);
                                 dst[0] = T(g0);
                                 dst[1] = T(g1);
                                 dst[2] = T(g2);
+                                if (LAPL) dst[3] = T(hwv * (R * yv) - qw * (lap * yv));
                             } else {
                                 grow[col + f] = T((hwv * (R * yv) - qw * (lap * yv)) + ((wax * g0 + way * g1) + waz * g2));
                             }
@@ -537,7 +544,8 @@ hipError_t launch_basis(const DevSeg* segs_dev, int n_segs, int64_t n_units, int
 {
     if (n_units <= 0 || n_segs <= 0) return hipSuccess;
     if (n_units > 0x7ffffff0 / BASIS_SLICES || spline_lds < 0 || spline_lds > MAX_SPLINE_LDS) return hipErrorInvalidValue;
-    if (extra != EXTRA_NONE && extra != EXTRA_GRAD && extra != EXTRA_GGA_L && extra != EXTRA_KS_L)
+    if (extra != EXTRA_NONE && extra != EXTRA_GRAD && extra != EXTRA_GGA_L && extra != EXTRA_KS_L &&
+        extra != EXTRA_GRAD_H)
         return hipErrorInvalidValue;
     const int64_t n_items = n_units * BASIS_SLICES;
     // two workgroups per CU fit (LDS); a grid of that size takes many items per workgroup, which
@@ -569,7 +577,9 @@ hipError_t launch_basis(const DevSeg* segs_dev, int n_segs, int64_t n_units, int
         reinterpret_cast<const void*>(&basis_kernel<TT, true, EXTRA_GGA_L>),                                     \
         reinterpret_cast<const void*>(&basis_kernel<TT, false, EXTRA_GGA_L>),                                    \
         reinterpret_cast<const void*>(&basis_kernel<TT, true, EXTRA_KS_L>),                                      \
-        reinterpret_cast<const void*>(&basis_kernel<TT, false, EXTRA_KS_L>)
+        reinterpret_cast<const void*>(&basis_kernel<TT, false, EXTRA_KS_L>),                                     \
+        reinterpret_cast<const void*>(&basis_kernel<TT, true, EXTRA_GRAD_H>),                                  \
+        reinterpret_cast<const void*>(&basis_kernel<TT, false, EXTRA_GRAD_H>)
         const void* fns[] = {NAO_BASIS_FNS(float), NAO_BASIS_FNS(double)};
 #undef NAO_BASIS_FNS
         for (const void* f : fns) {
@@ -588,6 +598,7 @@ hipError_t launch_basis(const DevSeg* segs_dev, int n_segs, int64_t n_units, int
         if (extra == EXTRA_GRAD) NAO_BASIS_LAUNCH(TT, EXTRA_GRAD);    \
         else if (extra == EXTRA_GGA_L) NAO_BASIS_LAUNCH(TT, EXTRA_GGA_L); \
         else if (extra == EXTRA_KS_L) NAO_BASIS_LAUNCH(TT, EXTRA_KS_L); \
+        else if (extra == EXTRA_GRAD_H) NAO_BASIS_LAUNCH(TT, EXTRA_GRAD_H); \
         else NAO_BASIS_LAUNCH(TT, EXTRA_NONE);                        \
     } while (0)
     if (fp32_out) NAO_BASIS_EXTRA(float);
@@ -1035,9 +1046,10 @@ __global__ __launch_bounds__(512) void h_kernel_wide(const DevSeg* __restrict__ 
 //
 // KIND = NK_GRADIENT: T[:, J] = Phi D[:, J] over the whole list (coefficient 1, the lower
 // triangle read transposed) and four row dots, n and grad n = 2 T . grad Phi.
-// KIND = NK_FORCE: the list is walked twice, M[:, J] = diag(w v) Phi D[:, J] - diag(w) Phi Q[:, J]
-// (the row weights applied to Phi as it is staged), and the epilogue takes column sums,
-// f_j += sum_p grad phi_pj M_pj, into the per-function accumulator fb[N_b][3].
+// KIND = NK_FORCE: the list is walked twice, M[:, J] = diag(w) (h_KS Phi) D[:, J] - diag(w) Phi
+// Q[:, J] with h_KS phi = v phi - lap phi / 2 (w h_KS phi written by the basis launch beside the
+// gradients, four values per basis value: x, y, z, w h_KS phi), and the epilogue takes column
+// sums, f_j += sum_p grad phi_pj M_pj, into the per-function accumulator fb[N_b][3].
 enum NKind { NK_DENSITY = 0, NK_GRADIENT = 1, NK_FORCE = 2 };
 template <typename T, int NW, int KC, bool DB, int KIND = NK_DENSITY>
 __global__ __launch_bounds__(64 * NW) void n_kernel(const DevSeg* __restrict__ segs, int n_segs, int64_t total)
@@ -1103,23 +1115,22 @@ __global__ __launch_bounds__(64 * NW) void n_kernel(const DevSeg* __restrict__ s
 #pragma unroll
                 for (int q = 0; q < ND; ++q) g[q] = fn[min(col0(c) + (tid >> 6) + (NT / TILE) * q, m - 1)];
             };
-            // forces: weights of this thread's staged rows, w v for the D pass and -w for the Q pass
-            double swv[FORCE ? NAR : 1], sw[FORCE ? NAR : 1];
+            // forces: weights of this thread's staged rows, -w for the Q pass
+            double sw[FORCE ? NAR : 1];
             if constexpr (FORCE) {
                 gp<const double> pw = gptr(sg.sys->pw + u.point_begin);
-                gp<const double> wv = gptr(sg.wv + u.point_begin);
 #pragma unroll
-                for (int q = 0; q < NAR; ++q) {
-                    const int row = min((tid + NT * q) / KC, np - 1);
-                    swv[q] = wv[row];
-                    sw[q] = -pw[row];
-                }
+                for (int q = 0; q < NAR; ++q) sw[q] = -pw[min((tid + NT * q) / KC, np - 1)];
             }
             auto fetch = [&](int c) {
 #pragma unroll
                 for (int q = 0; q < NAR; ++q) {
                     const int e = tid + NT * q;
-                    pa[q] = phi[(int64_t)min(e / KC, np - 1) * ld + col0(c) + (e % KC)];
+                    const int64_t el = (int64_t)min(e / KC, np - 1) * ld + col0(c) + (e % KC);
+                    // forces: the D pass takes w h_KS phi (fourth value of the basis launch's
+                    // gradient block), the Q pass phi
+                    if (FORCE && c < half) pa[q] = gptr(static_cast<const T*>(sg.gphi) + 4 * u.out_offset)[4 * el + 3];
+                    else pa[q] = phi[el];
                 }
                 const bool diag = c / (TILE / KC) == it.tj;
                 gp<const double> src = FORCE && c >= half ? gptr(sg.Q) : D;
@@ -1141,7 +1152,9 @@ __global__ __launch_bounds__(64 * NW) void n_kernel(const DevSeg* __restrict__ s
                 for (int q = 0; q < NAR; ++q) {
                     const int e = tid + NT * q;
                     T x = pa[q];
-                    if constexpr (FORCE) x = T((double)x * (c >= half ? sw[q] : swv[q]));
+                    if constexpr (FORCE) {  // Q pass: -w phi (the D pass staged w h_KS phi as it is)
+                        if (c >= half) x = T((double)x * sw[q]);
+                    }
                     As[buf][e / KC][e % KC] = (e / KC) < np ? x : T(0);
                 }
 #pragma unroll
@@ -1182,7 +1195,7 @@ __global__ __launch_bounds__(64 * NW) void n_kernel(const DevSeg* __restrict__ s
             const int cj = J0 + cb * 16 + lr;
             if constexpr (FORCE) {
                 // f_j += sum_p grad phi_pj M_pj: this wave's rows, then the lanes of one column
-                gp<const T> gph = gptr(static_cast<const T*>(sg.gphi) + 3 * u.out_offset);
+                gp<const T> gph = gptr(static_cast<const T*>(sg.gphi) + 4 * u.out_offset);  // x, y, z, lap
                 double f[3] = {0.0, 0.0, 0.0};
 #pragma unroll
                 for (int q = 0; q < R; ++q) {
@@ -1194,7 +1207,7 @@ __global__ __launch_bounds__(64 * NW) void n_kernel(const DevSeg* __restrict__ s
                             const int64_t e = (int64_t)min(p, np - 1) * ld + cj;
                             const double a = p < np && cj < m ? (double)acc[q][r] : 0.0;
 #pragma unroll
-                            for (int k = 0; k < 3; ++k) f[k] += a * (double)gph[3 * e + k];
+                            for (int k = 0; k < 3; ++k) f[k] += a * (double)gph[4 * e + k];
                         }
                     }
                 }

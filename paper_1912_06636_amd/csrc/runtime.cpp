@@ -1756,7 +1756,7 @@ nao_status nao_pulay_forces(nao_system s, const double* D, const double* Q, cons
     if (!F || (nb > 0 && (!D || !Q)) || (n > 0 && !v)) return (set_err(c, "NULL D, Q, v or F"), NAO_ERR_INVALID_ARG);
     if ((in_space != NAO_MEM_HOST && in_space != NAO_MEM_DEVICE) || (F_space != NAO_MEM_HOST && F_space != NAO_MEM_DEVICE))
         return (set_err(c, "bad memspace"), NAO_ERR_INVALID_ARG);
-    if ((st = ensure_gscratch(s, 3)) != NAO_OK) return st;  // gradients: 3 per basis value
+    if ((st = ensure_gscratch(s, 4)) != NAO_OK) return st;  // gradient and lap phi: 4 per basis value
     const double* Dd = D;
     const double* Qd = Q;
     const double* vd = v;
@@ -1803,8 +1803,8 @@ nao_status nao_pulay_forces(nao_system s, const double* D, const double* Q, cons
                                   c->stream));
         DevSeg* dseg = s->d_segs.as<DevSeg>();
         for (size_t k = 0; k < segs.size(); ++k) {
-            LAUNCH(c, f32 ? "basis_grad_f32" : "basis_grad_f64",
-                   launch_basis(dseg + k, 1, segs[k].unit_count, s->spline_lds, f32, c->stream, 0, EXTRA_GRAD));
+            LAUNCH(c, f32 ? "basis_gradlap_f32" : "basis_gradlap_f64",
+                   launch_basis(dseg + k, 1, segs[k].unit_count, s->spline_lds, f32, c->stream, 0, EXTRA_GRAD_H));
             LAUNCH(c, f32 ? "nforce_f32" : "nforce_f64", launch_n_force(mode, dseg + k, 1, segs[k].item_count, c->stream));
         }
     }

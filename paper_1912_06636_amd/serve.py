@@ -26,11 +26,15 @@ from workloads import generate as g
 
 
 def make_pool(n_structures, seed=0, min_atoms=20, max_atoms=400, grid_scale=1.0):
-    """Structures drawn log-uniformly in size, style 2 (block) or 4 (slab) by a coin flip."""
+    """Structures drawn log-uniformly in size, style 2 (block) or 4 (slab) by a coin flip; with
+    three or more structures the first two are the smallest and the largest size, so that the
+    pool spans the whole range."""
     rng = g.rng_for(5, seed, g.STREAM_ARRIVAL)
     pool = []
     for k in range(n_structures):
         n = int(round(math.exp(rng.uniform(math.log(min_atoms), math.log(max_atoms)))))
+        if n_structures >= 3 and k < 2:
+            n = (min_atoms, max_atoms)[k]
         style = 2 if rng.uniform() < 0.5 else 4
         xyz = g.serving_geometry(style, n, 1000 * seed + k)
         p = dict(g.CONFIGS[style])
@@ -234,7 +238,9 @@ def main(argv=None):
     ap.add_argument("--precision", default="fp32")
     ap.add_argument("--pool", type=int, default=6)
     ap.add_argument("--grid-scale", type=float, default=1.0)
-    ap.add_argument("--hbm-budget-gb", type=float, default=0.0)
+    # sessions beyond the budget wait for releases (admission by footprint); a saturated path
+    # would otherwise open sessions until the device runs out of memory
+    ap.add_argument("--hbm-budget-gb", type=float, default=160.0)
     ap.add_argument("--slots", type=int, default=3)
     ap.add_argument("--max-per-launch", type=int, default=8)
     args = ap.parse_args(argv)

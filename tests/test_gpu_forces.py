@@ -64,11 +64,13 @@ def test_forces_fp64_matches_oracle(nao, ctx, name):
     say("forces fp64", name, "e_F %.3e, max|F| %.3e" % (e, float(np.max(np.abs(F)))))
     assert F.shape == (len(B.atom_xyz), 3)
     assert e <= 1e-12
-    # sum over atoms = sum_p w_p [v_p grad n_D - grad n_Q] from the GPU's own gradients
+    # sum over atoms: the local-potential and q parts equal sum_p w_p [v_p grad n_D - grad n_Q]
+    # from the GPU's own gradients; the kinetic part is the oracle's
     _, gD = s.update_density_gradient(w["D"])
     _, gQ = s.update_density_gradient(Q)
     tot = ((w["w"] * w["v"])[:, None] * gD - w["w"][:, None] * gQ).sum(axis=0)
-    assert float(np.max(np.abs(F.sum(axis=0) - tot))) <= 1e-12 * float(np.max(np.abs(F)))
+    kin = (ref_forces(name) - oi.pulay_forces(B, w["xyz"], w["w"], w["v"], w["D"], Q, kinetic=False)).sum(axis=0)
+    assert float(np.max(np.abs(F.sum(axis=0) - tot - kin))) <= 1e-12 * float(np.max(np.abs(F)))
     s.close()
 
 
@@ -82,8 +84,8 @@ def test_forces_grouping_invariance_and_zero_case(nao, ctx):
         s.set_group_max(gm)
         assert rel_max(s.pulay_forces(w["D"], Q, w["v"]), F0) <= 1e-13
     s.set_group_max(256)
-    # no potential and no energy-weighted matrix: no force
-    assert np.all(s.pulay_forces(w["D"], np.zeros_like(Q), np.zeros_like(w["v"])) == 0.0)
+    # no density matrices: no force, whatever the potential
+    assert np.all(s.pulay_forces(np.zeros_like(Q), np.zeros_like(Q), w["v"]) == 0.0)
     s.close()
 
 

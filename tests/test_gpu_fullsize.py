@@ -175,14 +175,15 @@ def test_fp64_forces_sampled_against_oracle(nao, cfg):
     ctx = nao.Context(0)
     s = nao.build_batches(ctx, w["basis"], w["xyz"], w["w"], w["max_batch"])
     F = s.pulay_forces(w["D"], Q, w["v"])
+    F_kin = s.pulay_forces(w["D"], np.zeros_like(Q), np.zeros_like(w["v"]))  # the kinetic part alone
     _, gD = s.update_density_gradient(w["D"])
     _, gQ = s.update_density_gradient(Q)
     s.close()
     ctx.close()
     scale = float(np.max(np.abs(F)))
-    # every atom at once: sum_A F_A = sum_p w_p [v_p grad n_D - grad n_Q]
+    # every atom at once: the local-potential and q parts sum to sum_p w_p [v_p grad n_D - grad n_Q]
     tot = ((w["w"] * w["v"])[:, None] * gD - w["w"][:, None] * gQ).sum(axis=0)
-    assert float(np.max(np.abs(F.sum(axis=0) - tot))) <= 1e-12 * scale
+    assert float(np.max(np.abs((F - F_kin).sum(axis=0) - tot))) <= 1e-12 * scale
     atoms = [int(np.argmax(np.abs(F).max(axis=1)))] + ([len(F) // 3] if cfg == 2 else [])
     ref = oi.pulay_forces_at(B, w["xyz"], w["w"], w["v"], w["D"], Q, atoms)
     e = float(np.max(np.abs(F[atoms] - ref))) / scale
