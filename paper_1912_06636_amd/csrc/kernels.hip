@@ -164,12 +164,14 @@ __global__ __launch_bounds__(256, 2) void basis_kernel(const DevSeg* __restrict_
                                                        int spline_lds)
 {
     extern __shared__ double lds_spline[];
-    // plain basis values (EX = EXTRA_NONE): per wave, BASIS_WIN values of each of its 64 pairs,
-    // and per pair the unit-local offset of its first value and its value count
-    constexpr bool STAGE = EX == EXTRA_NONE;
+    // plain FP64 basis values (EX = EXTRA_NONE): per wave, BASIS_WIN values of each of its 64
+    // pairs, and per pair the unit-local offset of its first value and its value count (FP32
+    // values, half the bytes, are faster stored per pair directly)
+    constexpr bool STAGE = EX == EXTRA_NONE && sizeof(T) == 8;
     __shared__ double s_win[STAGE ? 4 * 64 * (BASIS_WIN + 1) : 1];
     __shared__ __align__(8) int32_t s_pair[STAGE ? 4 * 64 * 2 : 2];
-    __shared__ double s_pt[STAGE ? MAX_UNIT_POINTS / BASIS_SLICES : 1][3];  // the slice's points
+    constexpr int SPT = MAX_UNIT_POINTS / BASIS_SLICES;  // points of a slice staged at a time
+    __shared__ double s_pt[STAGE ? SPT : 1][3];  // the slice's points (a run of SPT at a time)
     __shared__ double s_atom[BASIS_ATOMS][4];  // x, y, z, (largest cutoff)^2
     __shared__ int32_t s_aspc[BASIS_ATOMS][2];  // species, first column in the unit
     __shared__ double s_par[BASIS_SHELLS][4];  // rmin, rcut^2, 1/Delta, ln rmin of the shell's radial
@@ -212,14 +214,16 @@ __global__ __launch_bounds__(256, 2) void basis_kernel(const DevSeg* __restrict_
             for (int i = tid; i < nsp; i += blockDim.x) lds_spline[i] = spl[i];
             table_of = S;
         }
-        if (STAGE) {
-            for (int i = tid; i < row1 - row0; i += blockDim.x) {
-                const int64_t p = u.point_begin + row0 + i;
+        // points of rows r0 .. r1 - 1 of the unit into s_pt
+        auto stage_points = [&](int r0, int r1) {
+            for (int i = tid; i < r1 - r0; i += blockDim.x) {
+                const int64_t p = u.point_begin + r0 + i;
                 s_pt[i][0] = gptr(S->px)[p];
                 s_pt[i][1] = gptr(S->py)[p];
                 s_pt[i][2] = gptr(S->pz)[p];
             }
-        }
+        };
+        if (STAGE) stage_points(row0, min(row1, row0 + SPT));
         if (staged) {
             for (int ai = tid; ai < na; ai += blockDim.x) {
                 const int atom = uat[ai];
@@ -393,19 +397,23 @@ __global__ __launch_bounds__(256, 2) void basis_kernel(const DevSeg* __restrict_
         // columns are consecutive in the row, so the values are staged in LDS, BASIS_WIN per pair
         // at a time, and written as contiguous runs of the rows (a store per value and lane would
         // touch a separate cache line per lane).
+        // the rows of the run in s_pt (a slice longer than SPT rows, which only a unit of more
+        // than MAX_UNIT_POINTS points has, is taken in several runs)
+        int run_row0 = row0;
+        int64_t run_pairs = (int64_t)(min(row1, row0 + SPT) - row0) * na;
         auto pairs_staged = [&](auto on_chip) {
             constexpr bool ST = decltype(on_chip)::value;
             constexpr int BW = BASIS_WIN, BWP = BASIS_WIN + 1;
             const int lane = tid & 63, wave = tid >> 6;
             double* win = &s_win[wave * 64 * BWP];
             int32_t* pinfo = &s_pair[wave * 64 * 2];
-            for (int64_t qb = tid - lane; qb < npairs; qb += blockDim.x) {  // wave-uniform trip count
+            for (int64_t qb = tid - lane; qb < run_pairs; qb += blockDim.x) {  // wave-uniform trip count
                 const int64_t q = qb + lane;
-                const bool valid = q < npairs;
+                const bool valid = q < run_pairs;
                 const int ql = (int)(valid ? q : qb);  // lanes past the end redo the wave's first pair
                 const int pq = ql / na;
                 const int ai = ql - pq * na;
-                const int pl = row0 + pq;
+                const int pl = run_row0 + pq;
                 const int atom = ST ? 0 : uat[ai];
                 const int col = ST ? s_aspc[ai][1] : ucol[ai];
                 const double ax = ST ? s_atom[ai][0] : axyz[4 * (int64_t)atom];
@@ -509,8 +517,18 @@ __global__ __launch_bounds__(256, 2) void basis_kernel(const DevSeg* __restrict_
             }
         };
         if constexpr (STAGE) {
-            if (staged) pairs_staged(std::true_type{});
-            else pairs_staged(std::false_type{});
+            for (int r0 = row0; r0 < row1; r0 += SPT) {
+                const int r1 = min(row1, r0 + SPT);
+                if (r0 != row0) {
+                    __syncthreads();  // every wave is done with the previous run's points
+                    stage_points(r0, r1);
+                    __syncthreads();
+                }
+                run_row0 = r0;
+                run_pairs = (int64_t)(r1 - r0) * na;
+                if (staged) pairs_staged(std::true_type{});
+                else pairs_staged(std::false_type{});
+            }
         } else {
             if (staged) pairs(std::true_type{});
             else pairs(std::false_type{});
@@ -659,6 +677,128 @@ template <> struct Mma<float> {
     }
     static __device__ inline int row(int lk, int r) { return 4 * lk + r; }
 };
+
+// Hamiltonian: per work item one 64x64 tile pair (I <= J) of a unit,
+//   H[I, J] += (w v Phi[:, I])^T Phi[:, J];
+// K loop over the unit's points in double-buffered chunks of 16 (register prefetch of the
+// next chunk while the MFMAs of the current one run); four waves, each a 32x32 quarter as
+// 2x2 MFMA blocks; FP64 atomics into the upper triangle of H.  T = FP32 accumulates a unit
+// (<= 256 points) in FP32 before the FP64 atomics.  The FP32 form (the staging below applies
+// w v once per value as it is stashed) is faster than the directly-loaded form; FP64 uses the
+// latter.
+template <typename T>
+__global__ __launch_bounds__(256, 4) void h_kernel(const DevSeg* __restrict__ segs, int n_segs, int64_t total)
+{
+    typedef Mma<T> M;
+    constexpr int HK = KCHUNK;              // points per chunk
+    constexpr int HQ = HK * TILE / 256;     // values per thread per chunk and operand
+    __shared__ T As[2][HK][TILE + 2];
+    __shared__ T Bs[2][HK][TILE + 2];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = wave >> 1, wc = wave & 1;
+    const int lr = lane & 15, lk = lane >> 4;
+    for (int64_t v_ = blockIdx.x; v_ < xcd_span(total); v_ += gridDim.x) {
+        const int64_t b = xcd_item(v_, total);
+        if (b >= total) continue;
+        const int s = find_segment(segs, n_segs, b, [](const DevSeg& g) { return g.item_prefix; });
+        const DevSeg& sg = segs[s];
+        const HItem it = static_cast<const HItem*>(sg.items)[sg.item_begin + (b - sg.item_prefix)];
+        const DevUnit u = sg.units[it.unit];
+        gp<const T> __restrict__ phi = gptr(static_cast<const T*>(sg.phi) + u.out_offset);
+        gp<const double> __restrict__ wv = gptr(sg.wv + u.point_begin);
+        const int np = u.n_points, ld = u.ld;
+        const int I0 = it.ti * TILE, J0 = it.tj * TILE;
+        const int n_chunks = (np + HK - 1) / HK;
+
+        if (np <= 0) continue;
+        // Loads are issued unconditionally (rows clamped into the unit) and only consumed at
+        // the stash after the next chunk's MFMAs, so that they stay in flight meanwhile.
+        T ra[HQ], rb[HQ];
+        double rw[HQ];
+        auto fetch = [&](int c) {
+#pragma unroll
+            for (int q = 0; q < HQ; ++q) {
+                const int e = tid + 256 * q;
+                const int pc = min(c * HK + (e >> 6), np - 1), col = e & 63;
+                gp<const T> rowp = phi + (int64_t)pc * ld;
+                ra[q] = rowp[I0 + col];
+                rb[q] = rowp[J0 + col];
+                rw[q] = wv[pc];
+            }
+        };
+        auto stash = [&](int c, int buf) {
+#pragma unroll
+            for (int q = 0; q < HQ; ++q) {
+                const int e = tid + 256 * q;
+                const bool ok = c * HK + (e >> 6) < np;
+                As[buf][e >> 6][e & 63] = ok ? T((double)ra[q] * rw[q]) : T(0);
+                Bs[buf][e >> 6][e & 63] = ok ? rb[q] : T(0);
+            }
+        };
+        // global indices of this lane's output rows and columns, needed only after the K loop
+        gp<const int32_t> __restrict__ fn = gptr(sg.unit_fn + u.fn_begin);
+        int32_t gI[2][4], gJ[2];
+#pragma unroll
+        for (int ib = 0; ib < 2; ++ib) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) gI[ib][r] = fn[min(I0 + wr * 32 + ib * 16 + M::row(lk, r), u.m - 1)];
+            gJ[ib] = fn[min(J0 + wc * 32 + ib * 16 + lr, u.m - 1)];
+        }
+
+        typename M::acc_t acc[2][2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] = M::zero();
+        // On a diagonal tile pair the wave of the strictly lower quarter only stages data.
+        auto k_loop = [&](auto with_mfma) {
+            fetch(0);
+            stash(0, 0);
+            __syncthreads();
+            for (int c = 0; c < n_chunks; ++c) {
+                const int buf = c & 1;
+                if (c + 1 < n_chunks) fetch(c + 1);
+                if (decltype(with_mfma)::value) {
+#pragma unroll
+                    for (int kk = 0; kk < HK / 4; ++kk) {
+                        const int kr = kk * 4 + lk;
+                        const T a0 = As[buf][kr][wr * 32 + lr];
+                        const T a1 = As[buf][kr][wr * 32 + 16 + lr];
+                        const T b0 = Bs[buf][kr][wc * 32 + lr];
+                        const T b1 = Bs[buf][kr][wc * 32 + 16 + lr];
+                        acc[0][0] = M::op(a0, b0, acc[0][0]);
+                        acc[0][1] = M::op(a0, b1, acc[0][1]);
+                        acc[1][0] = M::op(a1, b0, acc[1][0]);
+                        acc[1][1] = M::op(a1, b1, acc[1][1]);
+                    }
+                }
+                if (c + 1 < n_chunks) stash(c + 1, buf ^ 1);
+                __syncthreads();
+            }
+        };
+        const bool diag = it.ti == it.tj;
+        if (diag && wr > wc) {
+            k_loop(std::false_type{});
+            continue;
+        }
+        k_loop(std::true_type{});
+
+        gp<double> __restrict__ H = gptr(sg.H);
+        const int64_t ldh = sg.ld;
+#pragma unroll
+        for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+            for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = wr * 32 + ib * 16 + M::row(lk, r);
+                    const int col = wc * 32 + jb * 16 + lr;
+                    const int ci = I0 + row, cj = J0 + col;
+                    if (ci < u.m && cj < u.m && (!diag || row <= col))
+                        gadd(H + (int64_t)gI[ib][r] * ldh + gJ[jb], (double)acc[ib][jb][r]);
+                }
+    }
+}
 
 // Hamiltonian, staged by direct global-to-LDS loads: per work item one 64x64 tile pair (I <= J)
 // of a unit, H[I, J] += (w v Phi[:, I])^T Phi[:, J].  K = the unit's points in chunks of KC
@@ -1067,13 +1207,28 @@ __global__ __launch_bounds__(64 * NW) void n_kernel(const DevSeg* __restrict__ s
     static_assert(ND >= 1 && NA % 2 == 0 && RB % 4 == 0 && NT % TILE == 0 && TILE % KC == 0 && KC % 4 == 0,
                   "tile geometry");
     static_assert(!FORCE || RS * TILE * 3 <= 4 * MAX_UNIT_POINTS, "force partials fit in red");
-    __shared__ T As[NB][MAX_UNIT_POINTS][KC + 1];
+    // SLOT (density, gradient): basis values move as 16-byte slots (VPS values of one row), are
+    // staged in rows of KC values whose slots are XOR-swizzled by row, and are read back a whole
+    // slot per lane, so that the rows one 128-byte pass of a read touches fall in distinct banks
+    // (the MFMA steps take the chunk's columns in slot order, A and B alike).  The forces, whose D
+    // pass stages every fourth value of the basis launch's extra block, keep rows padded to KC + 1,
+    // and so does FP32 (faster so: its slots hold four columns, its rows half the bytes).
+    constexpr bool SLOT = !FORCE && sizeof(T) == 8;
+    constexpr int VPS = 16 / (int)sizeof(T);                 // values per slot
+    constexpr int SPR = KC / VPS;                            // slots per staged row
+    constexpr int ROWS_128B = 128 / (KC * (int)sizeof(T));   // staged rows per 128 bytes (the bank period)
+    constexpr int AW = SLOT ? KC : KC + 1;                   // staged row length
+    static_assert(!SLOT || (SPR >= 4 && SPR % 4 == 0 && ROWS_128B >= 1 && (SPR & (SPR - 1)) == 0), "slot geometry");
+    typedef T slot_t __attribute__((ext_vector_type(VPS)));
+    __shared__ __align__(16) T As[NB][MAX_UNIT_POINTS][AW];
     __shared__ T Bs[NB][KC][TILE + 2];
     constexpr int NQ = GRAD ? 4 : 1;                         // row dots: n, or n and the three gradient components
     __shared__ double red[NQ][4][MAX_UNIT_POINTS];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int cb = wave & 3, rh = wave >> 2;  // column block; row blocks rh, rh + RS, ...
     const int lr = lane & 15, lk = lane >> 4;
+    // staged position of slot j of row `row` within a buffer (SLOT)
+    auto a_slot = [](int row, int j) { return row * KC + ((j ^ ((row / ROWS_128B) & (SPR - 1))) * VPS); };
     for (int64_t v_ = blockIdx.x; v_ < xcd_span(total); v_ += gridDim.x) {
         const int64_t b = xcd_item(v_, total);
         if (b >= total) continue;
@@ -1107,7 +1262,11 @@ __global__ __launch_bounds__(64 * NW) void n_kernel(const DevSeg* __restrict__ s
             constexpr int F = decltype(rows_staged)::value;
             constexpr int R = decltype(rows_own)::value;
             constexpr int NAR = NA * F / RB;
-            T pa[NAR];
+            constexpr int ROWS = F * RS * 16;                           // rows staged
+            constexpr int NSL = SLOT ? (ROWS * SPR + NT - 1) / NT : 1;  // slots per thread
+            constexpr bool SL_ALL = ROWS * SPR % NT == 0;               // every thread takes NSL slots
+            T pa[SLOT ? 1 : NAR];
+            slot_t ps[NSL];
             double pd[ND];
             // list indices of the D rows: those of chunk c + 1 are loaded during chunk c
             int32_t gcur[ND], gnxt[ND];
@@ -1123,8 +1282,17 @@ __global__ __launch_bounds__(64 * NW) void n_kernel(const DevSeg* __restrict__ s
                 for (int q = 0; q < NAR; ++q) sw[q] = -pw[min((tid + NT * q) / KC, np - 1)];
             }
             auto fetch = [&](int c) {
+                if constexpr (SLOT) {
 #pragma unroll
-                for (int q = 0; q < NAR; ++q) {
+                    for (int q = 0; q < NSL; ++q) {
+                        const int e = tid + NT * q;  // slot e % SPR of row e / SPR
+                        if (SL_ALL || e < ROWS * SPR)
+                            ps[q] = *reinterpret_cast<gp<const slot_t>>(
+                                phi + (int64_t)min(e / SPR, np - 1) * ld + col0(c) + (e % SPR) * VPS);
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < (SLOT ? 0 : NAR); ++q) {
                     const int e = tid + NT * q;
                     const int64_t el = (int64_t)min(e / KC, np - 1) * ld + col0(c) + (e % KC);
                     // forces: the D pass takes w h_KS phi (fourth value of the basis launch's
@@ -1148,8 +1316,17 @@ __global__ __launch_bounds__(64 * NW) void n_kernel(const DevSeg* __restrict__ s
 #pragma unroll
                 for (int q = 0; q < ND; ++q) gcur[q] = gnxt[q];
                 const bool diag = c / (TILE / KC) == it.tj;
+                if constexpr (SLOT) {
 #pragma unroll
-                for (int q = 0; q < NAR; ++q) {
+                    for (int q = 0; q < NSL; ++q) {
+                        const int e = tid + NT * q;
+                        if (SL_ALL || e < ROWS * SPR)
+                            *reinterpret_cast<slot_t*>(&As[buf][0][0] + a_slot(e / SPR, e % SPR)) =
+                                e / SPR < np ? ps[q] : slot_t(T(0));
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < (SLOT ? 0 : NAR); ++q) {
                     const int e = tid + NT * q;
                     T x = pa[q];
                     if constexpr (FORCE) {  // Q pass: -w phi (the D pass staged w h_KS phi as it is)
@@ -1173,11 +1350,29 @@ __global__ __launch_bounds__(64 * NW) void n_kernel(const DevSeg* __restrict__ s
             stash(0, 0);
             __syncthreads();
             auto mfma_chunk = [&](int buf) {
+                if constexpr (SLOT) {
+                    // lane group lk reads slots lk + 4 h of its rows; step (h, e) takes column
+                    // VPS (lk + 4 h) + e of the chunk
 #pragma unroll
-                for (int kk = 0; kk < KC / 4; ++kk) {
-                    const T bv = Bs[buf][kk * 4 + lk][cb * 16 + lr];
+                    for (int h = 0; h < SPR / 4; ++h) {
+                        slot_t a[R > 0 ? R : 1];
 #pragma unroll
-                    for (int q = 0; q < R; ++q) acc[q] = M::op(As[buf][(RS * q + rh) * 16 + lr][kk * 4 + lk], bv, acc[q]);
+                        for (int q = 0; q < R; ++q)
+                            a[q] = *reinterpret_cast<const slot_t*>(&As[buf][0][0] + a_slot((RS * q + rh) * 16 + lr, lk + 4 * h));
+#pragma unroll
+                        for (int e = 0; e < VPS; ++e) {
+                            const T bv = Bs[buf][VPS * (lk + 4 * h) + e][cb * 16 + lr];
+#pragma unroll
+                            for (int q = 0; q < R; ++q) acc[q] = M::op(a[q][e], bv, acc[q]);
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int kk = 0; kk < KC / 4; ++kk) {
+                        const T bv = Bs[buf][kk * 4 + lk][cb * 16 + lr];
+#pragma unroll
+                        for (int q = 0; q < R; ++q) acc[q] = M::op(As[buf][(RS * q + rh) * 16 + lr][kk * 4 + lk], bv, acc[q]);
+                    }
                 }
             };
             // straight-line body (the last chunk peeled off) so that the scheduler can
@@ -1635,7 +1830,7 @@ hipError_t launch_h(Mode mode, const DevSeg* segs_dev, int n_segs, int64_t n_ite
     const dim3 g(grid_for(n_items, max_grid)), b(256);
     switch (mode) {
     case MODE_FP64: hipLaunchKernelGGL((h_kernel_dma<double, 16, 3>), g, b, 0, st, segs_dev, n_segs, n_items); break;
-    case MODE_FP32: hipLaunchKernelGGL((h_kernel_dma<float, 16, 3>), g, b, 0, st, segs_dev, n_segs, n_items); break;
+    case MODE_FP32: hipLaunchKernelGGL(h_kernel<float>, g, b, 0, st, segs_dev, n_segs, n_items); break;
     case MODE_BF16X3: hipLaunchKernelGGL(h_kernel_bf16<2>, g, b, 0, st, segs_dev, n_segs, n_items); break;
     case MODE_BF16X6: hipLaunchKernelGGL(h_kernel_bf16<3>, g, b, 0, st, segs_dev, n_segs, n_items); break;
     default: return hipErrorInvalidValue;

@@ -49,6 +49,17 @@ def make_pool(n_structures, seed=0, min_atoms=20, max_atoms=400, grid_scale=1.0)
     return pool
 
 
+def measure_pool(nao, pool):
+    """Work measure U = sum_b |B_b| m_b^2 of every pool structure (both operations use the same
+    batches), stored as w["units"]."""
+    home = nao.Context(0)
+    for w in pool:
+        s = nao.build_batches(home, w["basis"], w["xyz"], w["w"], w["max_batch"])
+        w["units"] = s.work_units()
+        s.close()
+    home.close()
+
+
 class DensityStager:
     """Fresh seeded D = C C^T per (session, iteration), built on the GPU with torch and zeroed
     between centres farther apart than d_max (input staging, not part of the method).
@@ -128,10 +139,13 @@ class DensityStager:
 
 
 def run(nao, torch, pool, lam, duration_s, max_requests, path, precision="fp32", n_slots=3,
-        max_per_launch=8, hbm_budget=0, seed=0, log=None):
+        max_per_launch=8, hbm_budget=0, seed=0, log=None, max_sessions=24):
     """One serving run; returns a dict with latency percentiles and throughput.  Latency runs
     from a request's arrival to its results being complete on the device: the driver's delay
-    before the submit plus the server's submit-to-done time."""
+    before the submit (waiting for a session, a staged D) plus the server's submit-to-done time.
+    At most max_sessions sessions are open at once: an arrival that finds every open session busy
+    and the limit reached waits in the driver's queue (a saturated path would otherwise open a
+    session, and stage its next D, for every arrival)."""
     dev = torch.device("cuda:0")
     rng = np.random.default_rng(np.random.SeedSequence([5, seed, g.STREAM_ARRIVAL, int(lam * 1000)]))
     home = nao.Context(0, hbm_budget=hbm_budget)
@@ -148,16 +162,25 @@ def run(nao, torch, pool, lam, duration_s, max_requests, path, precision="fp32",
     t0 = time.perf_counter()
     next_arrival = t0 + rng.exponential(1.0 / lam)
     vbuf = {}
+    queue = []          # arrival times waiting for a session
+    open_now, max_queue = 0, 0
     while True:
         now = time.perf_counter()
         if now - t0 > duration_s or done >= max_requests:
             break
-        while now >= next_arrival and submitted < max_requests:
-            arrival = next_arrival
+        while now >= next_arrival and submitted + len(queue) < max_requests:
+            queue.append(next_arrival)
+            next_arrival += rng.exponential(1.0 / lam)
+        max_queue = max(max_queue, len(queue))
+        while queue:
             free = [s for s in sessions if not s["busy"] and s["k"] < s["K"]]
+            if not free and open_now >= max_sessions:
+                break
+            arrival = queue.pop(0)
             if free:
                 s = min(free, key=lambda x: x["opened"])
             else:
+                open_now += 1
                 w = pool[int(rng.integers(len(pool)))]
                 sid = srv.open_session(w["basis"], w["xyz"], w["w"], w["max_batch"])
                 s = dict(sid=sid, work=w, k=0, K=int(rng.integers(10, 41)), busy=False, opened=now,
@@ -178,7 +201,6 @@ def run(nao, torch, pool, lam, duration_s, max_requests, path, precision="fp32",
             s["busy"] = True
             s["k"] += 1
             submitted += 1
-            next_arrival += rng.exponential(1.0 / lam)
         srv.step()
         for tk in list(tickets):
             st, t_sub, t_start, t_end = srv.poll(tk)
@@ -193,6 +215,7 @@ def run(nao, torch, pool, lam, duration_s, max_requests, path, precision="fp32",
                 if s["k"] >= s["K"]:
                     srv.close_session(s["sid"])
                     vbuf.pop(s["sid"], None)
+                    open_now -= 1
         time.sleep(0.0002)
     elapsed = time.perf_counter() - t0
     # requests still waiting are dropped with the server; wait only for the running ones
@@ -214,7 +237,8 @@ def run(nao, torch, pool, lam, duration_s, max_requests, path, precision="fp32",
                p50_ms=round(float(np.percentile(lat, 50)), 2) if len(lat) else None,
                p99_ms=round(float(np.percentile(lat, 99)), 2) if len(lat) else None,
                staging_busy_s=round(stager.busy_s, 2), staging_wait_s=round(wait_s, 2),
-               sessions=len(sessions), backlog_at_end=int(backlog))
+               sessions=len(sessions), backlog_at_end=int(backlog) + len(queue),
+               driver_queue_max=int(max_queue))
     if log:
         log("serve %s" % out)
     return out
@@ -250,13 +274,7 @@ def main(argv=None):
 
     t0 = time.time()
     pool = make_pool(args.pool, grid_scale=args.grid_scale)
-    # work measure per request (both operations use the same batches)
-    home = nao.Context(0)
-    for w in pool:
-        s = nao.build_batches(home, w["basis"], w["xyz"], w["w"], w["max_batch"])
-        w["units"] = s.work_units()
-        s.close()
-    home.close()
+    measure_pool(nao, pool)
     log("pool of %d structures (%s atoms) ready in %.1f s" % (
         len(pool), [len(w["basis"]["atom_xyz"]) for w in pool], time.time() - t0))
     for path in args.paths:

@@ -79,3 +79,16 @@ def case(name):
                n=oi.density(B, w["xyz"], w["D"]))
     ref["Ne"] = oi.electron_count(w["w"], ref["n"])
     return w, B, ref
+
+
+@functools.lru_cache(maxsize=None)
+def wide_list_case():
+    """150 atoms 0.5 A apart with 32 functions each (4800 functions): the units near the centre
+    list every function, more than the density kernel stages the list of on chip (4096).  Only
+    the density is referenced (H over 4800 functions costs the oracle minutes)."""
+    k = np.arange(6) * 0.5
+    xyz = np.array([[x, y, z] for z in k[:5] for y in k[:5] for x in k])
+    basis = g.make_basis(xyz, np.zeros(len(xyz), np.int32), [(0, 0, 1, 1, 2, 2, 3, 3)], [4.0], 7, 11)
+    w = _finish(basis, xyz, 4.0, 2, 6, seed=11, n_occ=40, max_batch=64)
+    B = ob.Basis(w["basis"])
+    return w, B, oi.density(B, w["xyz"], w["D"])

@@ -51,6 +51,29 @@ def test_batches_and_lists_bit_exact(nao, ctx, name):
     s.close()
 
 
+@pytest.mark.parametrize("name,max_batch", [("two_species", 300), ("two_species", 4096), ("multitile", 1000)])
+def test_eval_basis_large_batches(nao, ctx, name, max_batch):
+    """Batches of more points than an execution group: each batch is evaluated as one unit whose
+    point slices are longer than the basis kernel stages at a time."""
+    w, B, ref = case(name)
+    say("eval_basis large batches", name, max_batch)
+    s = nao.build_batches(ctx, w["basis"], w["xyz"], w["w"], max_batch)
+    perm, bp, lp, li = s.get_batches()
+    assert int(np.max(np.diff(bp))) > 256
+    phi, ptr = s.eval_basis()
+    worst = scale = 0.0
+    for b in range(s.n_batches):
+        ref_b = oi.batch_phi(B, w["xyz"], perm, bp, lp, li, b)
+        got = phi[ptr[b]:ptr[b + 1]].reshape(ref_b.shape)
+        if ref_b.size:
+            worst = max(worst, float(np.max(np.abs(got - ref_b))))
+            scale = max(scale, float(np.max(np.abs(ref_b))))
+            assert np.all(got[ref_b == 0.0] == 0.0)
+    say("eval_basis large batches", name, max_batch, "abs err", worst, "scale", scale)
+    assert worst <= 1e-13 * scale
+    s.close()
+
+
 @pytest.mark.parametrize("name", ["config1", "multitile", "two_species"])
 def test_eval_basis_matches_oracle(nao, ctx, name):
     w, B, ref = case(name)
