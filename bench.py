@@ -31,11 +31,12 @@ PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0, "bf16x6": 2500.0}  # TFLO
 KERNELS_SRC = os.path.join(ROOT, "paper_1912_06636_amd", "csrc", "kernels.hip")
 # HBM bytes per launch of the contraction kernels on the default workload, from two rocprofv3
 # --pmc passes (FETCH_SIZE, WRITE_SIZE) over "bench.py --steps 1 --warmup 0 --h-tile 64
-# --no-cpu-baseline --calibrate-copy 1024", each counter scaled by its reading of the 1 GiB
-# plain copy made in that run.  Valid only for the kernel source it was taken on (sha256).
-TRAFFIC = {"sha256": "fde1e6b66bb516aef319c6624617b7236cb5804fa77c4899712fe37f9fe52f48",
+# --no-cpu-baseline --no-plain --serve-seconds 0 --calibrate-copy 1024", each counter scaled by
+# its reading of the 1 GiB plain copy made in that run.  Valid only for the kernel source it was
+# taken on (sha256).
+TRAFFIC = {"sha256": "f1c4c5a05c6dbb2cccc33bf2a85cfba955d61311441f3d9889617ffc3b96f028",
            "workload": "slab375", "precision": "fp64", "h_tile": 64, "group_max": 256,
-           "bytes_per_launch": {"n_f64": 5.910e9, "h_f64": 6.019e9}}
+           "bytes_per_launch": {"n_f64": 5.905e9, "h_f64": 6.019e9}}
 WORKLOADS = {
     "slab375": (4, "375-atom layered slab, 28 NAO/atom (10,500 basis functions, l<=3, 6 A cutoff), "
                    "60x434 grid/atom = 9,765,000 points, octree batches <= 256"),
@@ -333,12 +334,22 @@ def main():
     value = 2.0 * U / (ms_per_step * 1e-3) / 1e9
     log("step %.2f ms (n %.2f, H %.2f), %.1f Gpt*basis^2/s" % (ms_per_step, np.mean(n_ms), np.mean(h_ms), value))
 
-    # per-kernel timing on the same stream (separate pass: events around every launch)
+    # per-kernel timing (separate pass: events around every launch, on the stream it runs on); the
+    # basis launches run beside the contractions (the library's default), so a contraction's time
+    # includes its share of the GPU with them; a second pass with the overlap off times every
+    # kernel alone
     ctx.profile(True)
     step()
     prof = ctx.profile_read()
     ctx.profile(False)
     log("kernels: " + ", ".join("%s %d x %.2f ms" % (k, c, t) for k, (c, t) in prof.items()))
+    ctx.set_overlap(False)
+    ctx.profile(True)
+    step()
+    prof_alone = ctx.profile_read()
+    ctx.profile(False)
+    ctx.set_overlap(True)
+    log("kernels alone: " + ", ".join("%s %d x %.2f ms" % (k, c, t) for k, (c, t) in prof_alone.items()))
     prec = args.precision
     sfx = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3", "bf16x6": "bf16x6"}[prec]
     # algorithmic flops of one call, summed over the octree batches, as the method counts them:
@@ -369,6 +380,9 @@ def main():
         if "n_" + sfx in cands:
             t = cands["n_" + sfx][1]
             roofline["kernels"]["n_" + sfx]["frac_half_credit"] = round(credit_n_half / (t * 1e-3) / 1e12 / peak, 4)
+        roofline["kernels_alone"] = {k: {"launches": c, "ms": round(t, 3),
+                                         "frac": round(credit[k] / (t * 1e-3) / 1e12 / peak, 4)}
+                                     for k, (c, t) in prof_alone.items() if k in credit}
     # the whole step (basis evaluation included) against the same peak
     step_flops = credit["h_" + sfx] + credit["n_" + sfx]
     roofline_step = {"flops": step_flops, "achieved": round(step_flops / (ms_per_step * 1e-3) / 1e12, 3),
@@ -490,6 +504,7 @@ def main():
         log("local Pulay forces: %.2f ms (%.2fx the density alone); kernels: %s" % (ms, ms / n_mean, kern))
         del Q, F
 
+    n_points, n_basis, n_batches = int(sysm.n_points), int(sysm.n_basis), int(sysm.n_batches)
     serving = None
     if args.serve_seconds > 0:
         # continuous-batching serving of SCF-iteration requests (density update then H) for a pool
@@ -525,11 +540,11 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3", "bf16x6": "bf16x6"}[prec],
         "data": "synthetic (seeded generator; shapes of the paper's workloads)",
-        "config": {"workload": args.workload, "description": desc, "n_points": int(sysm.n_points),
-                   "n_basis": int(sysm.n_basis), "n_batches": int(sysm.n_batches), "units_per_op": U,
+        "config": {"workload": args.workload, "description": desc, "n_points": n_points,
+                   "n_basis": n_basis, "n_batches": n_batches, "units_per_op": U,
                    "group_max": args.group_max, "h_tile": args.h_tile, "precision": prec,
                    "batcher": args.batcher, "max_batch": max_batch,
-                   "mean_batch": round(float(sysm.n_points) / max(1, sysm.n_batches), 2),
+                   "mean_batch": round(float(n_points) / max(1, n_batches), 2),
                    "autotuned": tuned},
         "latency_ms": {"p50": round(float(np.percentile(step_ms, 50)), 3),
                        "p99": round(float(np.percentile(step_ms, 99)), 3)},

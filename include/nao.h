@@ -113,9 +113,22 @@ nao_status nao_ctx_synchronize(nao_ctx ctx);
 /* Bytes currently allocated by the context and its budget (0 = none). */
 nao_status nao_ctx_memory(nao_ctx ctx, size_t* used_bytes, size_t* budget_bytes);
 
+/* Overlap of basis evaluation with the contractions in nao_integrate_h and nao_update_density
+ * (the overlap of independent work that the paper's GPU variants exploit, Section "GPGPU
+ * Acceleration of the Real-Space Domain Decomposition Algorithm"): with more than one block of
+ * basis values, the basis launch of block k + 1 runs on a second stream of the context (default
+ * priority) into a second buffer while the contraction of block k runs on the context stream,
+ * ordered by events; the context stream still ends after every launch of the call, so callers
+ * synchronize on it alone.  On by default (NAO_OVERLAP=0 in the environment turns it off for
+ * contexts created afterwards).  The second buffer, as large as the basis scratch, is charged to
+ * the budget; a call for which it does not fit runs serially.  enable = 0 turns it off and frees
+ * the buffer (after the work in flight), any other value turns it on. */
+nao_status nao_ctx_set_overlap(nao_ctx ctx, int enable);
+
 /* Per-kernel timing (the per-operation timings the paper reports, at kernel granularity).
  * nao_ctx_profile(ctx, 1) starts recording: every kernel launch of the context is then
- * bracketed by HIP events on the context stream; (ctx, 0) stops.  Starting also clears
+ * bracketed by HIP events on the stream it runs on (the context stream, or the second stream of
+ * an overlapped basis evaluation); (ctx, 0) stops.  Starting also clears
  * what was recorded.  nao_ctx_profile_read synchronizes the stream and reports, per kernel
  * name (at most max_entries, names as 32-byte NUL-terminated strings in names), the number
  * of launches and their summed duration in milliseconds; n_entries receives the count. */

@@ -52,6 +52,17 @@ struct nao_ctx_s {
     size_t gscratch_bytes = 0;
     size_t scratch_cap_elems = 0;
     double* wsum = nullptr;      // WSUM_BLOCKS partials + 1 result
+    // Overlap of the basis evaluation of block k + 1 with the contraction of block k (density
+    // update and Hamiltonian): odd blocks take their basis values in a second buffer, the basis
+    // launches run on a second stream (default priority), and events order the two (see
+    // run_blocks).  Off with NAO_OVERLAP=0, or when the second buffer does not fit the budget.
+    bool overlap = true;
+    hipStream_t stream2 = nullptr;
+    double* scratch2 = nullptr;
+    size_t scratch2_elems = 0;
+    hipEvent_t ev_start = nullptr;       // the context stream's work before the operation
+    hipEvent_t ev_ready[2] = {};         // basis values of the last block of each buffer written
+    hipEvent_t ev_done[2] = {};          // contraction of the last block of each buffer done
     int n_systems = 0;
     // per-kernel timing
     bool prof = false;
@@ -106,23 +117,24 @@ hipEvent_t take_event(nao_ctx c)
     return e;
 }
 
-// Launch through f(); when profiling, bracket it with events on the context stream.
+// Launch through f(); when profiling, bracket it with events on the stream it launches on.
 template <typename F>
-hipError_t timed(nao_ctx c, const char* name, F&& f)
+hipError_t timed(nao_ctx c, const char* name, hipStream_t st, F&& f)
 {
     if (!c->prof) return f();
     hipEvent_t a = take_event(c), b = take_event(c);
     if (!a || !b) return hipErrorOutOfMemory;
-    hipError_t e = hipEventRecord(a, c->stream);
+    hipError_t e = hipEventRecord(a, st);
     if (e != hipSuccess) return e;
     e = f();
     if (e != hipSuccess) return e;
-    e = hipEventRecord(b, c->stream);
+    e = hipEventRecord(b, st);
     c->recs.push_back({name, a, b});
     return e;
 }
 
-#define LAUNCH(ctx, name, call) HIP_TRY(ctx, timed(ctx, name, [&]() { return (call); }))
+#define LAUNCH(ctx, name, call) HIP_TRY(ctx, timed(ctx, name, (ctx)->stream, [&]() { return (call); }))
+#define LAUNCH_ON(ctx, name, st, call) HIP_TRY(ctx, timed(ctx, name, st, [&]() { return (call); }))
 
 nao_status dev_alloc(nao_ctx c, size_t bytes, void** out)
 {
@@ -707,7 +719,7 @@ nao_status run_many_impl(nao_ctx c, const nao_work* work, int64_t n_work, nao_pr
     if (capture) {
         for (ManyPlan* m : c->many)
             if (m->key == key && m->exec) {
-                HIP_TRY(c, timed(c, "graph", [&]() { return hipGraphLaunch(m->exec, c->stream); }));
+                HIP_TRY(c, timed(c, "graph", c->stream, [&]() { return hipGraphLaunch(m->exec, c->stream); }));
                 return NAO_OK;
             }
     }
@@ -763,7 +775,7 @@ nao_status run_many_impl(nao_ctx c, const nao_work* work, int64_t n_work, nao_pr
         c->many.erase(c->many.begin());
     }
     c->many.push_back(m);
-    HIP_TRY(c, timed(c, "graph", [&]() { return hipGraphLaunch(m->exec, c->stream); }));
+    HIP_TRY(c, timed(c, "graph", c->stream, [&]() { return hipGraphLaunch(m->exec, c->stream); }));
     return NAO_OK;
 }
 
@@ -819,6 +831,7 @@ nao_status nao_ctx_create(int device, void* hip_stream, size_t hbm_budget_bytes,
         const long v = std::atol(e);
         if (v >= 0 && v <= 64) c->persistent_per_cu = v;
     }
+    if (const char* e = std::getenv("NAO_OVERLAP")) c->overlap = std::atol(e) != 0;
     c->scratch_cap_elems = scratch_cap_from_env();
     e = hipSetDevice(device);
     if (e == hipSuccess) e = noalloc_scratch_init(device);  // the device address of the fixed scratch
@@ -858,9 +871,14 @@ void nao_ctx_destroy(nao_ctx c)
     (void)hipStreamSynchronize(c->stream);
     for (auto& sp : c->spare) dev_free(c, sp.first, sp.second);
     c->spare.clear();
+    if (c->stream2) (void)hipStreamSynchronize(c->stream2);
     dev_free(c, c->scratch, c->scratch_elems * sizeof(double));
+    dev_free(c, c->scratch2, c->scratch2_elems * sizeof(double));
     dev_free(c, c->gscratch, c->gscratch_bytes);
     dev_free(c, c->wsum, (WSUM_BLOCKS + 1) * sizeof(double));
+    for (hipEvent_t e : {c->ev_start, c->ev_ready[0], c->ev_ready[1], c->ev_done[0], c->ev_done[1]})
+        if (e) (void)hipEventDestroy(e);
+    if (c->stream2) (void)hipStreamDestroy(c->stream2);
     for (auto& r : c->recs) {
         (void)hipEventDestroy(r.a);
         (void)hipEventDestroy(r.b);
@@ -914,6 +932,21 @@ nao_status nao_ctx_memory(nao_ctx c, size_t* used, size_t* budget)
     }
     if (used) *used = c->used;
     if (budget) *budget = c->budget;
+    return NAO_OK;
+}
+
+nao_status nao_ctx_set_overlap(nao_ctx c, int enable)
+{
+    nao_status st = check_ctx(c);
+    if (st != NAO_OK) return st;
+    c->overlap = enable != 0;
+    if (!c->overlap && c->scratch2) {
+        HIP_TRY(c, hipStreamSynchronize(c->stream2));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        dev_free(c, c->scratch2, c->scratch2_elems * sizeof(double));
+        c->scratch2 = nullptr;
+        c->scratch2_elems = 0;
+    }
     return NAO_OK;
 }
 
@@ -1388,6 +1421,46 @@ static nao_status check_prec(nao_ctx c, nao_precision p)
     return (set_err(c, "unknown precision"), NAO_ERR_INVALID_ARG);
 }
 
+// Second stream, events and a second basis buffer of `elems` values for the overlapped block
+// loop; false (and the loop runs on one stream) when overlap is off, the buffer would exceed the
+// budget or a resource cannot be had.
+static bool overlap_ready(nao_ctx c, size_t elems)
+{
+    if (!c->overlap) return false;
+    if (!c->stream2) {
+        bool ok = hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking) == hipSuccess;
+        for (hipEvent_t* e : {&c->ev_start, &c->ev_ready[0], &c->ev_ready[1], &c->ev_done[0], &c->ev_done[1]})
+            ok = ok && hipEventCreateWithFlags(e, hipEventDisableTiming) == hipSuccess;
+        if (!ok) {
+            (void)hipGetLastError();
+            c->overlap = false;
+            return false;
+        }
+    }
+    if (elems > c->scratch2_elems) {
+        const size_t bytes = elems * sizeof(double), held = c->scratch2_elems * sizeof(double);
+        if (c->budget && c->used - held + bytes > c->budget) return false;
+        if (c->scratch2) {  // earlier operations may still read or write it
+            (void)hipStreamSynchronize(c->stream2);
+            (void)hipStreamSynchronize(c->stream);
+        }
+        dev_free(c, c->scratch2, held);
+        c->scratch2 = nullptr;
+        c->scratch2_elems = 0;
+        void* p = nullptr;
+        if (dev_alloc(c, bytes, &p) != NAO_OK) return false;
+        c->scratch2 = static_cast<double*>(p);
+        c->scratch2_elems = elems;
+    }
+    return true;
+}
+
+// The block loop of a density update or Hamiltonian integration: per block, the basis values of
+// its units (unless resident), then the contraction.  With more than one block and overlap on,
+// block k's basis values go to buffer k % 2 and its basis launch to the second stream, which
+// waits for the contraction of block k - 2 (the last reader of that buffer); the contraction of
+// block k waits for its basis launch.  The context stream thus ends after every launch of the
+// operation, so callers synchronize on it alone.
 static nao_status run_blocks(nao_system s, bool ham, nao_precision prec, const double* wv, const double* D, double* H,
                              double* n)
 {
@@ -1401,8 +1474,12 @@ static nao_status run_blocks(nao_system s, bool ham, nao_precision prec, const d
     const bool res = s->resident && s->d_phi_res.p && s->res_off.size() == s->blocks.size();
     const int kind = f32 ? 1 : 0;
     const bool evaluate = !res || s->res_kind != kind;
+    size_t need = 0;
+    for (const Block& b : s->blocks) need = std::max(need, (size_t)b.phi_elems);
+    const bool ovl = !res && s->blocks.size() > 1 && overlap_ready(c, need);
     for (size_t k = 0; k < s->blocks.size(); ++k) {
         DevSeg g = make_seg(s, s->blocks[k], ham, wide);
+        if (ovl && (k & 1)) g.phi = c->scratch2;
         if (res) g.phi = static_cast<char*>(s->d_phi_res.p) + s->res_off[k] * (f32 ? sizeof(float) : sizeof(double));
         g.wv = wv;
         g.D = D;
@@ -1415,15 +1492,28 @@ static nao_status run_blocks(nao_system s, bool ham, nao_precision prec, const d
                               c->stream));
     DevSeg* dseg = s->d_segs.as<DevSeg>();
     if (res && evaluate) s->res_kind = -1;  // marked valid only once every block is enqueued
+    if (ovl) {  // the second stream starts after the context stream's work so far (inputs, table)
+        HIP_TRY(c, hipEventRecord(c->ev_start, c->stream));
+        HIP_TRY(c, hipStreamWaitEvent(c->stream2, c->ev_start, 0));
+    }
     for (size_t k = 0; k < segs.size(); ++k) {
-        if (staged && evaluate)
+        const int buf = (int)(k & 1);
+        if (ovl) {
+            if (k >= 2) HIP_TRY(c, hipStreamWaitEvent(c->stream2, c->ev_done[buf], 0));
+            LAUNCH_ON(c, f32 ? "basis_f32" : "basis_f64", c->stream2,
+                      launch_basis(dseg + k, 1, segs[k].unit_count, s->spline_lds, f32, c->stream2));
+            HIP_TRY(c, hipEventRecord(c->ev_ready[buf], c->stream2));
+            HIP_TRY(c, hipStreamWaitEvent(c->stream, c->ev_ready[buf], 0));
+        } else if (staged && evaluate) {
             LAUNCH(c, f32 ? "basis_f32" : "basis_f64",
                    launch_basis(dseg + k, 1, segs[k].unit_count, s->spline_lds, f32, c->stream));
+        }
         if (ham)
             LAUNCH(c, kname(true, prec),
                    launch_h(mode, dseg + k, 1, segs[k].item_count, c->stream, 0, wide ? 128 : TILE));
         else
             LAUNCH(c, kname(false, prec), launch_n(mode, dseg + k, 1, segs[k].item_count, c->stream));
+        if (ovl) HIP_TRY(c, hipEventRecord(c->ev_done[buf], c->stream));
     }
     if (res) s->res_kind = kind;
     return NAO_OK;

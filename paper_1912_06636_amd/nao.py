@@ -66,6 +66,7 @@ _sig("nao_ctx_set_stream", _S, _vp, _vp)
 _sig("nao_ctx_stream", _vp, _vp)
 _sig("nao_ctx_synchronize", _S, _vp)
 _sig("nao_ctx_memory", _S, _vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t))
+_sig("nao_ctx_set_overlap", _S, _vp, ctypes.c_int)
 _sig("nao_ctx_profile", _S, _vp, ctypes.c_int)
 _sig("nao_ctx_profile_read", _S, _vp, ctypes.c_int32, ctypes.c_char_p, _c_i64p, _c_dp, _c_i32p)
 _sig("nao_plan_create", _S, ctypes.POINTER(BasisDesc), ctypes.c_int64, _c_dp, ctypes.c_int32, ctypes.POINTER(_vp))
@@ -109,7 +110,7 @@ _sig("nao_server_destroy", None, _vp)
 
 EXPORTED = [
     "nao_ctx_create", "nao_ctx_destroy", "nao_last_error", "nao_ctx_set_stream", "nao_ctx_stream",
-    "nao_ctx_synchronize", "nao_ctx_memory", "nao_ctx_profile", "nao_ctx_profile_read", "nao_plan_create", "nao_plan_info", "nao_plan_get_batches",
+    "nao_ctx_synchronize", "nao_ctx_memory", "nao_ctx_set_overlap", "nao_ctx_profile", "nao_ctx_profile_read", "nao_plan_create", "nao_plan_info", "nao_plan_get_batches",
     "nao_plan_destroy", "nao_build_batches", "nao_system_set_group_max", "nao_system_set_h_tile", "nao_system_autotune", "nao_system_info", "nao_get_batches",
     "nao_system_work", "nao_eval_basis", "nao_integrate_h", "nao_update_density", "nao_update_density_gradient", "nao_integrate_h_gga",
     "nao_pulay_forces", "nao_integrate_h_ks", "nao_plan_create_ex", "nao_build_batches_ex",
@@ -247,6 +248,10 @@ class Context:
         u, b = ctypes.c_size_t(), ctypes.c_size_t()
         _check(_lib.nao_ctx_memory(self.handle, ctypes.byref(u), ctypes.byref(b)), self.handle)
         return u.value, b.value
+
+    def set_overlap(self, enable=True):
+        """nao_ctx_set_overlap: basis evaluation of the next block beside the current contraction."""
+        _check(_lib.nao_ctx_set_overlap(self.handle, 1 if enable else 0), self.handle)
 
     def profile(self, enable=True):
         _check(_lib.nao_ctx_profile(self.handle, 1 if enable else 0), self.handle)

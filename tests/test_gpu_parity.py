@@ -244,6 +244,31 @@ def test_invalid_arguments_return_codes(nao, ctx):
     s.close()
 
 
+@pytest.mark.parametrize("overlap", ["1", "0"])
+def test_small_blocks(nao, monkeypatch, overlap):
+    """Basis values in blocks of at most 16 MB, several per operation: the basis evaluation of
+    block k + 1 overlapped with the contraction of block k on a second stream (NAO_OVERLAP=1, the
+    default) or the two serial on one stream (0); both against the oracle."""
+    w, B, ref = case("multitile")
+    monkeypatch.setenv("NAO_SCRATCH_MB", "16")
+    monkeypatch.setenv("NAO_OVERLAP", overlap)
+    say("small blocks, overlap", overlap)
+    c = nao.Context(0)
+    c.profile(True)
+    s = nao.build_batches(c, w["basis"], w["xyz"], w["w"], w["max_batch"])
+    for prec, tol in (("fp64", TOL), ("fp32", 1e-6)):
+        for rep in range(2):  # the second call reuses the buffers and the events
+            eH = rel_max(s.integrate_h(w["v"], precision=prec), ref["H"])
+            en = rel_max(s.update_density(w["D"], precision=prec), ref["n"])
+            say("small blocks, overlap", overlap, prec, rep, "H %.2e n %.2e" % (eH, en))
+            assert eH <= tol and en <= tol
+    prof = c.profile_read()
+    say("small blocks, overlap", overlap, "launches", prof)
+    assert prof["basis_f64"][0] >= 4 * 3  # four operations of three or more blocks each
+    s.close()
+    c.close()
+
+
 # Stated error bounds of the reduced-precision modes against the FP64 oracle (normwise max
 # relative error of H, n and N_e); the measured values are printed for the record.
 PREC_TOL = {"fp32": 1e-5, "bf16x3": 1e-4, "bf16x6": 1e-5}
