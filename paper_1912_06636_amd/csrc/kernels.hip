@@ -692,8 +692,11 @@ __global__ __launch_bounds__(256, 4) void h_kernel(const DevSeg* __restrict__ se
     typedef Mma<T> M;
     constexpr int HK = KCHUNK;              // points per chunk
     constexpr int HQ = HK * TILE / 256;     // values per thread per chunk and operand
-    __shared__ T As[2][HK][TILE + 2];
-    __shared__ T Bs[2][HK][TILE + 2];
+    // rows padded so that two consecutive rows start half a 128-byte bank period apart: the MFMA
+    // reads of a wave's first 32 lanes (16 columns of two rows) then fall in distinct banks
+    constexpr int PAD = 64 / (int)sizeof(T);
+    __shared__ T As[2][HK][TILE + PAD];
+    __shared__ T Bs[2][HK][TILE + PAD];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = wave >> 1, wc = wave & 1;
     const int lr = lane & 15, lk = lane >> 4;
@@ -1545,13 +1548,17 @@ __global__ __launch_bounds__(256, 3) void h_kernel_bf16(const DevSeg* __restrict
         const int I0 = it.ti * TILE, J0 = it.tj * TILE;
         const int n_chunks = (np + BK - 1) / BK;
 
+        // this thread's column of both operands and its NQ = 8 consecutive points of a chunk, so
+        // that every part is stashed as one 16-byte run of a column (loads: a wave reads 64
+        // consecutive columns of one point)
+        static_assert(NQ == 8, "eight points per thread");
+        const int col = tid & 63, p0 = NQ * (tid >> 6);
         float ra[NQ], rb[NQ];
         double rw[NQ];
         auto fetch = [&](int c) {
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
-                const int e = tid + 256 * q;
-                const int pc = min(c * BK + (e >> 6), np - 1), col = e & 63;
+                const int pc = min(c * BK + p0 + q, np - 1);
                 gp<const float> rowp = phi + (int64_t)pc * ld;
                 ra[q] = rowp[I0 + col];
                 rb[q] = rowp[J0 + col];
@@ -1559,19 +1566,23 @@ __global__ __launch_bounds__(256, 3) void h_kernel_bf16(const DevSeg* __restrict
             }
         };
         auto stash = [&](int c, int buf) {
+            bf8 pa[NS], pb[NS];
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
-                const int e = tid + 256 * q;
-                const int r = e >> 6, col = e & 63;
-                const bool ok = c * BK + r < np;
-                __bf16 pa[NS], pb[NS];
-                split_bf16<NS>(ok ? (float)((double)ra[q] * rw[q]) : 0.f, pa);
-                split_bf16<NS>(ok ? rb[q] : 0.f, pb);
+                const bool ok = c * BK + p0 + q < np;
+                __bf16 xa[NS], xb[NS];
+                split_bf16<NS>(ok ? (float)((double)ra[q] * rw[q]) : 0.f, xa);
+                split_bf16<NS>(ok ? rb[q] : 0.f, xb);
 #pragma unroll
                 for (int t = 0; t < NS; ++t) {
-                    As[buf][t][col][r] = pa[t];
-                    Bs[buf][t][col][r] = pb[t];
+                    pa[t][q] = xa[t];
+                    pb[t][q] = xb[t];
                 }
+            }
+#pragma unroll
+            for (int t = 0; t < NS; ++t) {
+                *reinterpret_cast<bf8*>(&As[buf][t][col][p0]) = pa[t];
+                *reinterpret_cast<bf8*>(&Bs[buf][t][col][p0]) = pb[t];
             }
         };
         gp<const int32_t> __restrict__ fn = gptr(sg.unit_fn + u.fn_begin);
