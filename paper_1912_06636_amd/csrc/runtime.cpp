@@ -505,6 +505,7 @@ struct ManyPlan {
     std::vector<nao_work> entries;
     std::vector<int64_t> wv_off;  // per entry: offset into the w*v arena (H entries)
     nao_precision prec = NAO_FP64;
+    bool overlap = false;  // odd chunks in the second buffer, basis launches on the second stream
     DevArray d_segs, d_wv;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -571,6 +572,41 @@ nao_status grow_scratch(nao_ctx c, size_t elems)
     return NAO_OK;
 }
 
+// Second stream, events and a second basis buffer of `elems` values for the overlapped block
+// loops (run_blocks, nao_run_many); false (and the loop runs on one stream) when overlap is off,
+// the buffer would exceed the budget or a resource cannot be had.
+static bool overlap_ready(nao_ctx c, size_t elems)
+{
+    if (!c->overlap) return false;
+    if (!c->stream2) {
+        bool ok = hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking) == hipSuccess;
+        for (hipEvent_t* e : {&c->ev_start, &c->ev_ready[0], &c->ev_ready[1], &c->ev_done[0], &c->ev_done[1]})
+            ok = ok && hipEventCreateWithFlags(e, hipEventDisableTiming) == hipSuccess;
+        if (!ok) {
+            (void)hipGetLastError();
+            c->overlap = false;
+            return false;
+        }
+    }
+    if (elems > c->scratch2_elems) {
+        const size_t bytes = elems * sizeof(double), held = c->scratch2_elems * sizeof(double);
+        if (c->budget && c->used - held + bytes > c->budget) return false;
+        if (c->scratch2) {  // earlier operations may still read or write it, captured plans hold it
+            many_forget(c, nullptr);
+            (void)hipStreamSynchronize(c->stream2);
+            (void)hipStreamSynchronize(c->stream);
+        }
+        dev_free(c, c->scratch2, held);
+        c->scratch2 = nullptr;
+        c->scratch2_elems = 0;
+        void* p = nullptr;
+        if (dev_alloc(c, bytes, &p) != NAO_OK) return false;
+        c->scratch2 = static_cast<double*>(p);
+        c->scratch2_elems = elems;
+    }
+    return true;
+}
+
 namespace {
 
 nao_status many_build(nao_ctx c, const nao_work* work, int64_t n_work, nao_precision prec, ManyPlan* m)
@@ -619,13 +655,17 @@ nao_status many_build(nao_ctx c, const nao_work* work, int64_t n_work, nao_preci
     }
     const bool f32 = prec != NAO_FP64;
     const size_t esz = f32 ? sizeof(float) : sizeof(double);
+    size_t n_chunks = 0;
+    for (auto& ch : chunks) n_chunks += !ch.empty();
+    m->overlap = n_chunks > 1 && overlap_ready(c, c->scratch_elems);
     for (auto& ch : chunks) {
         if (ch.empty()) continue;
         ManyPlan::Chunk k;
         k.all_off = m->segs.size();
+        double* buf = m->overlap && (m->chunks.size() & 1) ? c->scratch2 : c->scratch;
         for (Pending& p : ch) {
             DevSeg g = p.g;
-            g.phi = static_cast<char*>(static_cast<void*>(c->scratch)) + p.phi * esz;
+            g.phi = static_cast<char*>(static_cast<void*>(buf)) + p.phi * esz;
             g.unit_prefix = k.units;
             k.units += g.unit_count;
             m->segs.push_back(g);
@@ -690,15 +730,33 @@ nao_status many_enqueue(nao_ctx c, ManyPlan* m)
         lds = std::max(lds, w.sys->spline_lds);
     }
     if (!all_fit) lds = 0;
-    for (const auto& k : m->chunks) {
-        if (staged)
+    // with overlap, as in run_blocks: chunk k's basis launch on the second stream after the
+    // contraction of chunk k - 2 (the last reader of its buffer), its contractions after it (the
+    // fork and join are events, which a captured graph records as dependencies)
+    const bool ovl = m->overlap;
+    if (ovl) {
+        HIP_TRY(c, hipEventRecord(c->ev_start, c->stream));
+        HIP_TRY(c, hipStreamWaitEvent(c->stream2, c->ev_start, 0));
+    }
+    for (size_t ki = 0; ki < m->chunks.size(); ++ki) {
+        const auto& k = m->chunks[ki];
+        const int buf = (int)(ki & 1);
+        if (ovl) {
+            if (ki >= 2) HIP_TRY(c, hipStreamWaitEvent(c->stream2, c->ev_done[buf], 0));
+            LAUNCH_ON(c, f32 ? "basis_f32" : "basis_f64", c->stream2,
+                      launch_basis(d + k.all_off, (int)k.all_n, k.units, lds, f32, c->stream2, grid));
+            HIP_TRY(c, hipEventRecord(c->ev_ready[buf], c->stream2));
+            HIP_TRY(c, hipStreamWaitEvent(c->stream, c->ev_ready[buf], 0));
+        } else if (staged) {
             LAUNCH(c, f32 ? "basis_f32" : "basis_f64",
                    launch_basis(d + k.all_off, (int)k.all_n, k.units, lds, f32, c->stream, grid));
+        }
         for (int t = 0; t < 2; ++t)
             if (k.h_n[t])
                 LAUNCH(c, kname(true, m->prec), launch_h(mode, d + k.h_off[t], (int)k.h_n[t], k.h_items[t], c->stream,
                                                          grid, t == 0 ? TILE : 128));
         if (k.n_n) LAUNCH(c, kname(false, m->prec), launch_n(mode, d + k.n_off, (int)k.n_n, k.n_items, c->stream, grid));
+        if (ovl) HIP_TRY(c, hipEventRecord(c->ev_done[buf], c->stream));
     }
     for (const nao_work& w : m->entries)
         if (w.op == 0) LAUNCH(c, "mirror", launch_mirror(w.out, w.sys->basis.n_basis, c->stream));
@@ -941,6 +999,7 @@ nao_status nao_ctx_set_overlap(nao_ctx c, int enable)
     if (st != NAO_OK) return st;
     c->overlap = enable != 0;
     if (!c->overlap && c->scratch2) {
+        many_forget(c, nullptr);  // captured plans hold the buffer
         HIP_TRY(c, hipStreamSynchronize(c->stream2));
         HIP_TRY(c, hipStreamSynchronize(c->stream));
         dev_free(c, c->scratch2, c->scratch2_elems * sizeof(double));
@@ -1419,40 +1478,6 @@ static nao_status check_prec(nao_ctx c, nao_precision p)
 {
     if (p == NAO_FP64 || p == NAO_FP32 || p == NAO_BF16X3 || p == NAO_BF16X6) return NAO_OK;
     return (set_err(c, "unknown precision"), NAO_ERR_INVALID_ARG);
-}
-
-// Second stream, events and a second basis buffer of `elems` values for the overlapped block
-// loop; false (and the loop runs on one stream) when overlap is off, the buffer would exceed the
-// budget or a resource cannot be had.
-static bool overlap_ready(nao_ctx c, size_t elems)
-{
-    if (!c->overlap) return false;
-    if (!c->stream2) {
-        bool ok = hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking) == hipSuccess;
-        for (hipEvent_t* e : {&c->ev_start, &c->ev_ready[0], &c->ev_ready[1], &c->ev_done[0], &c->ev_done[1]})
-            ok = ok && hipEventCreateWithFlags(e, hipEventDisableTiming) == hipSuccess;
-        if (!ok) {
-            (void)hipGetLastError();
-            c->overlap = false;
-            return false;
-        }
-    }
-    if (elems > c->scratch2_elems) {
-        const size_t bytes = elems * sizeof(double), held = c->scratch2_elems * sizeof(double);
-        if (c->budget && c->used - held + bytes > c->budget) return false;
-        if (c->scratch2) {  // earlier operations may still read or write it
-            (void)hipStreamSynchronize(c->stream2);
-            (void)hipStreamSynchronize(c->stream);
-        }
-        dev_free(c, c->scratch2, held);
-        c->scratch2 = nullptr;
-        c->scratch2_elems = 0;
-        void* p = nullptr;
-        if (dev_alloc(c, bytes, &p) != NAO_OK) return false;
-        c->scratch2 = static_cast<double*>(p);
-        c->scratch2_elems = elems;
-    }
-    return true;
 }
 
 // The block loop of a density update or Hamiltonian integration: per block, the basis values of
