@@ -186,3 +186,37 @@ def test_many_on_a_caller_stream_with_electron_counts(env):
         assert rel_max(H.cpu().numpy(), s.integrate_h(w["v"])) <= 1e-12
     with pytest.raises(nao.NaoError):
         ctx.run_many(work, capture_graph=True, electrons=True)
+
+
+def test_overlap_toggle_with_captured_plans(monkeypatch):
+    """Chunks in two buffers with the basis launches on a second stream (blocks of at most 16 MB:
+    several chunks): captured and eager results equal the oracle with the overlap on, after it is
+    turned off (the second buffer is freed, so captured plans that hold it must be dropped) and
+    after it is turned on again."""
+    import torch
+    from paper_1912_06636_amd import nao
+    monkeypatch.setenv("NAO_SCRATCH_MB", "16")
+    say("overlap toggle with captured plans")
+    ctx = nao.Context(0)
+    w1, B1, ref1 = case("multitile")
+    w2, B2, ref2 = case("config1")
+    s1 = nao.build_batches(ctx, w1["basis"], w1["xyz"], w1["w"], w1["max_batch"])
+    s2 = nao.build_batches(ctx, w2["basis"], w2["xyz"], w2["w"], w2["max_batch"])
+    t1, t2 = _tensors(torch, w1, s1), _tensors(torch, w2, s2)
+    work = [(s1, "h", t1[0], t1[2]), (s1, "n", t1[1], t1[3]), (s2, "n", t2[1], t2[3]), (s2, "h", t2[0], t2[2])]
+    for state in ("on", "off", "on again"):
+        ctx.set_overlap(state != "off")
+        for capture in (True, True, False):
+            for t in (t1, t2):
+                t[2].fill_(9.0)
+                t[3].fill_(-9.0)
+            torch.cuda.synchronize()
+            ctx.run_many(work, capture_graph=capture)
+            ctx.synchronize()
+            for t, ref in ((t1, ref1), (t2, ref2)):
+                eH, en = rel_max(t[2].cpu().numpy(), ref["H"]), rel_max(t[3].cpu().numpy(), ref["n"])
+                say("overlap", state, "capture", capture, "H %.2e n %.2e" % (eH, en))
+                assert eH <= 1e-12 and en <= 1e-12
+    s2.close()
+    s1.close()
+    ctx.close()
