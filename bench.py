@@ -34,7 +34,7 @@ KERNELS_SRC = os.path.join(ROOT, "paper_1912_06636_amd", "csrc", "kernels.hip")
 # --no-cpu-baseline --no-plain --serve-seconds 0 --calibrate-copy 1024", each counter scaled by
 # its reading of the 1 GiB plain copy made in that run.  Valid only for the kernel source it was
 # taken on (sha256).
-TRAFFIC = {"sha256": "f1c4c5a05c6dbb2cccc33bf2a85cfba955d61311441f3d9889617ffc3b96f028",
+TRAFFIC = {"sha256": "01eec34281ecbcdbe3c7fcccd97f6832c0fd3f8f54e1a63009ab5d320af2fdf7",
            "workload": "slab375", "precision": "fp64", "h_tile": 64, "group_max": 256,
            "bytes_per_launch": {"n_f64": 5.905e9, "h_f64": 6.019e9}}
 WORKLOADS = {
