@@ -60,6 +60,8 @@ struct nao_ctx_s {
     hipStream_t stream2 = nullptr;
     double* scratch2 = nullptr;
     size_t scratch2_elems = 0;
+    void* gscratch2 = nullptr;           // second buffer of gscratch (the extended operations)
+    size_t gscratch2_bytes = 0;
     hipEvent_t ev_start = nullptr;       // the context stream's work before the operation
     hipEvent_t ev_ready[2] = {};         // basis values of the last block of each buffer written
     hipEvent_t ev_done[2] = {};          // contraction of the last block of each buffer done
@@ -607,6 +609,55 @@ static bool overlap_ready(nao_ctx c, size_t elems)
     return true;
 }
 
+// A second extra-value buffer of `bytes` for the overlapped loops of the extended operations;
+// false (serial loop) when it would exceed the budget or cannot be had.
+static bool overlap_gscratch(nao_ctx c, size_t bytes)
+{
+    if (bytes <= c->gscratch2_bytes) return true;
+    if (c->budget && c->used - c->gscratch2_bytes + bytes > c->budget) return false;
+    if (c->gscratch2) {  // earlier operations may still read or write it
+        (void)hipStreamSynchronize(c->stream2);
+        (void)hipStreamSynchronize(c->stream);
+    }
+    dev_free(c, c->gscratch2, c->gscratch2_bytes);
+    c->gscratch2 = nullptr;
+    c->gscratch2_bytes = 0;
+    void* p = nullptr;
+    if (dev_alloc(c, bytes, &p) != NAO_OK) return false;
+    c->gscratch2 = p;
+    c->gscratch2_bytes = bytes;
+    return true;
+}
+
+// The block loop of an operation: per block k, basis(k, stream) (skipped when bname is null)
+// and then contract(k) on the context stream.  With ovl, block k's basis launch runs on the
+// second stream, after the context stream's work before the loop and after the contraction of
+// block k - 2 (the last reader of its buffers), and block k's contraction waits for it; the
+// context stream thus ends after every launch of the loop.
+template <typename FB, typename FC>
+static nao_status block_loop(nao_ctx c, size_t n_blocks, bool ovl, const char* bname, const char* cname, FB&& basis,
+                             FC&& contract)
+{
+    if (ovl) {
+        HIP_TRY(c, hipEventRecord(c->ev_start, c->stream));
+        HIP_TRY(c, hipStreamWaitEvent(c->stream2, c->ev_start, 0));
+    }
+    for (size_t k = 0; k < n_blocks; ++k) {
+        const int buf = (int)(k & 1);
+        if (ovl) {
+            if (k >= 2) HIP_TRY(c, hipStreamWaitEvent(c->stream2, c->ev_done[buf], 0));
+            LAUNCH_ON(c, bname, c->stream2, basis(k, c->stream2));
+            HIP_TRY(c, hipEventRecord(c->ev_ready[buf], c->stream2));
+            HIP_TRY(c, hipStreamWaitEvent(c->stream, c->ev_ready[buf], 0));
+        } else if (bname) {
+            LAUNCH(c, bname, basis(k, c->stream));
+        }
+        LAUNCH(c, cname, contract(k));
+        if (ovl) HIP_TRY(c, hipEventRecord(c->ev_done[buf], c->stream));
+    }
+    return NAO_OK;
+}
+
 namespace {
 
 nao_status many_build(nao_ctx c, const nao_work* work, int64_t n_work, nao_precision prec, ManyPlan* m)
@@ -933,6 +984,7 @@ void nao_ctx_destroy(nao_ctx c)
     dev_free(c, c->scratch, c->scratch_elems * sizeof(double));
     dev_free(c, c->scratch2, c->scratch2_elems * sizeof(double));
     dev_free(c, c->gscratch, c->gscratch_bytes);
+    dev_free(c, c->gscratch2, c->gscratch2_bytes);
     dev_free(c, c->wsum, (WSUM_BLOCKS + 1) * sizeof(double));
     for (hipEvent_t e : {c->ev_start, c->ev_ready[0], c->ev_ready[1], c->ev_done[0], c->ev_done[1]})
         if (e) (void)hipEventDestroy(e);
@@ -1005,6 +1057,13 @@ nao_status nao_ctx_set_overlap(nao_ctx c, int enable)
         dev_free(c, c->scratch2, c->scratch2_elems * sizeof(double));
         c->scratch2 = nullptr;
         c->scratch2_elems = 0;
+    }
+    if (!c->overlap && c->gscratch2) {
+        HIP_TRY(c, hipStreamSynchronize(c->stream2));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        dev_free(c, c->gscratch2, c->gscratch2_bytes);
+        c->gscratch2 = nullptr;
+        c->gscratch2_bytes = 0;
     }
     return NAO_OK;
 }
@@ -1517,29 +1576,14 @@ static nao_status run_blocks(nao_system s, bool ham, nao_precision prec, const d
                               c->stream));
     DevSeg* dseg = s->d_segs.as<DevSeg>();
     if (res && evaluate) s->res_kind = -1;  // marked valid only once every block is enqueued
-    if (ovl) {  // the second stream starts after the context stream's work so far (inputs, table)
-        HIP_TRY(c, hipEventRecord(c->ev_start, c->stream));
-        HIP_TRY(c, hipStreamWaitEvent(c->stream2, c->ev_start, 0));
-    }
-    for (size_t k = 0; k < segs.size(); ++k) {
-        const int buf = (int)(k & 1);
-        if (ovl) {
-            if (k >= 2) HIP_TRY(c, hipStreamWaitEvent(c->stream2, c->ev_done[buf], 0));
-            LAUNCH_ON(c, f32 ? "basis_f32" : "basis_f64", c->stream2,
-                      launch_basis(dseg + k, 1, segs[k].unit_count, s->spline_lds, f32, c->stream2));
-            HIP_TRY(c, hipEventRecord(c->ev_ready[buf], c->stream2));
-            HIP_TRY(c, hipStreamWaitEvent(c->stream, c->ev_ready[buf], 0));
-        } else if (staged && evaluate) {
-            LAUNCH(c, f32 ? "basis_f32" : "basis_f64",
-                   launch_basis(dseg + k, 1, segs[k].unit_count, s->spline_lds, f32, c->stream));
-        }
-        if (ham)
-            LAUNCH(c, kname(true, prec),
-                   launch_h(mode, dseg + k, 1, segs[k].item_count, c->stream, 0, wide ? 128 : TILE));
-        else
-            LAUNCH(c, kname(false, prec), launch_n(mode, dseg + k, 1, segs[k].item_count, c->stream));
-        if (ovl) HIP_TRY(c, hipEventRecord(c->ev_done[buf], c->stream));
-    }
+    nao_status st = block_loop(
+        c, segs.size(), ovl, staged && evaluate ? (f32 ? "basis_f32" : "basis_f64") : nullptr, kname(ham, prec),
+        [&](size_t k, hipStream_t q) { return launch_basis(dseg + k, 1, segs[k].unit_count, s->spline_lds, f32, q); },
+        [&](size_t k) {
+            return ham ? launch_h(mode, dseg + k, 1, segs[k].item_count, c->stream, 0, wide ? 128 : TILE)
+                       : launch_n(mode, dseg + k, 1, segs[k].item_count, c->stream);
+        });
+    if (st != NAO_OK) return st;
     if (res) s->res_kind = kind;
     return NAO_OK;
 }
@@ -1692,6 +1736,17 @@ nao_status nao_update_density(nao_system s, const double* D, nao_memspace D_spac
 }
 
 // Extra per-block scratch beside the basis values: `per_value` FP64 slots per basis value.
+// Both second buffers for an overlapped extended operation whose extra block holds per_value
+// values per basis value (call after ensure_gscratch).
+static bool overlap_ext(nao_system s, int per_value)
+{
+    nao_ctx c = s->ctx;
+    if (s->blocks.size() < 2) return false;
+    size_t need = 0;
+    for (const Block& b : s->blocks) need = std::max(need, (size_t)b.phi_elems);
+    return overlap_ready(c, need) && overlap_gscratch(c, need * per_value * sizeof(double));
+}
+
 static nao_status ensure_gscratch(nao_system s, int per_value)
 {
     nao_ctx c = s->ctx;
@@ -1745,6 +1800,7 @@ static nao_status integrate_h_with_l(nao_system s, const double* v, const double
         LAUNCH(c, "wa", launch_wa(s->d_pw.as<double>(), s->d_perm.as<int32_t>(), ad, s->d_wa.as<double>(), n, c->stream));
     const Mode mode = exec_mode(c, prec);
     const bool f32 = prec != NAO_FP64;
+    const bool ovl = overlap_ext(s, 1);
     std::vector<DevSeg> segs;
     for (const Block& b : s->blocks) {
         DevSeg g = make_seg(s, b, true, false);
@@ -1752,6 +1808,10 @@ static nao_status integrate_h_with_l(nao_system s, const double* v, const double
         g.wa = has_a ? s->d_wa.as<double>() : nullptr;
         g.H = Hd;
         g.gphi = c->gscratch;
+        if (ovl && (segs.size() & 1)) {
+            g.phi = c->scratch2;
+            g.gphi = c->gscratch2;
+        }
         segs.push_back(g);
     }
     if (!segs.empty()) {
@@ -1760,10 +1820,11 @@ static nao_status integrate_h_with_l(nao_system s, const double* v, const double
         DevSeg* dseg = s->d_segs.as<DevSeg>();
         const char* bname = ks ? (f32 ? "basis_ks_f32" : "basis_ks_f64") : (f32 ? "basis_gga_f32" : "basis_gga_f64");
         const char* hname = ks ? (f32 ? "hks_f32" : "hks_f64") : (f32 ? "hgga_f32" : "hgga_f64");
-        for (size_t k = 0; k < segs.size(); ++k) {
-            LAUNCH(c, bname, launch_basis(dseg + k, 1, segs[k].unit_count, s->spline_lds, f32, c->stream, 0, extra));
-            LAUNCH(c, hname, launch_h_gga(mode, dseg + k, 1, segs[k].item_count, c->stream));
-        }
+        st = block_loop(
+            c, segs.size(), ovl, bname, hname,
+            [&](size_t k, hipStream_t q) { return launch_basis(dseg + k, 1, segs[k].unit_count, s->spline_lds, f32, q, 0, extra); },
+            [&](size_t k) { return launch_h_gga(mode, dseg + k, 1, segs[k].item_count, c->stream); });
+        if (st != NAO_OK) return st;
     }
     LAUNCH(c, "mirror", launch_mirror(Hd, nb, c->stream));
     if (H_space == NAO_MEM_HOST) {
@@ -1831,6 +1892,7 @@ nao_status nao_update_density_gradient(nao_system s, const double* D, nao_memspa
     LAUNCH(c, "fill", launch_fill(gd, 3 * n, 0.0, c->stream));
     const Mode mode = exec_mode(c, prec);
     const bool f32 = prec != NAO_FP64;
+    const bool ovl = overlap_ext(s, 3);
     std::vector<DevSeg> segs;
     for (const Block& b : s->blocks) {
         DevSeg g = make_seg(s, b, false);
@@ -1838,17 +1900,23 @@ nao_status nao_update_density_gradient(nao_system s, const double* D, nao_memspa
         g.n = nd;
         g.gn = gd;
         g.gphi = c->gscratch;
+        if (ovl && (segs.size() & 1)) {
+            g.phi = c->scratch2;
+            g.gphi = c->gscratch2;
+        }
         segs.push_back(g);
     }
     if (!segs.empty()) {
         HIP_TRY(c, hipMemcpyAsync(s->d_segs.p, segs.data(), segs.size() * sizeof(DevSeg), hipMemcpyHostToDevice,
                                   c->stream));
         DevSeg* dseg = s->d_segs.as<DevSeg>();
-        for (size_t k = 0; k < segs.size(); ++k) {
-            LAUNCH(c, f32 ? "basis_grad_f32" : "basis_grad_f64",
-                   launch_basis(dseg + k, 1, segs[k].unit_count, s->spline_lds, f32, c->stream, 0, EXTRA_GRAD));
-            LAUNCH(c, f32 ? "ngrad_f32" : "ngrad_f64", launch_n_grad(mode, dseg + k, 1, segs[k].item_count, c->stream));
-        }
+        st = block_loop(
+            c, segs.size(), ovl, f32 ? "basis_grad_f32" : "basis_grad_f64", f32 ? "ngrad_f32" : "ngrad_f64",
+            [&](size_t k, hipStream_t q) {
+                return launch_basis(dseg + k, 1, segs[k].unit_count, s->spline_lds, f32, q, 0, EXTRA_GRAD);
+            },
+            [&](size_t k) { return launch_n_grad(mode, dseg + k, 1, segs[k].item_count, c->stream); });
+        if (st != NAO_OK) return st;
     }
     if (out_space == NAO_MEM_HOST && n > 0) {
         HIP_TRY(c, hipMemcpyAsync(nout, nd, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
@@ -1903,6 +1971,7 @@ nao_status nao_pulay_forces(nao_system s, const double* D, const double* Q, cons
     LAUNCH(c, "wv", launch_wv(s->d_pw.as<double>(), s->d_perm.as<int32_t>(), vd, s->d_wv.as<double>(), n, c->stream));
     const Mode mode = exec_mode(c, prec);
     const bool f32 = prec != NAO_FP64;
+    const bool ovl = overlap_ext(s, 4);
     std::vector<DevSeg> segs;
     for (const Block& b : s->blocks) {
         DevSeg g = make_seg(s, b, false);
@@ -1911,17 +1980,23 @@ nao_status nao_pulay_forces(nao_system s, const double* D, const double* Q, cons
         g.wv = s->d_wv.as<double>();
         g.fb = s->d_fb.as<double>();
         g.gphi = c->gscratch;
+        if (ovl && (segs.size() & 1)) {
+            g.phi = c->scratch2;
+            g.gphi = c->gscratch2;
+        }
         segs.push_back(g);
     }
     if (!segs.empty()) {
         HIP_TRY(c, hipMemcpyAsync(s->d_segs.p, segs.data(), segs.size() * sizeof(DevSeg), hipMemcpyHostToDevice,
                                   c->stream));
         DevSeg* dseg = s->d_segs.as<DevSeg>();
-        for (size_t k = 0; k < segs.size(); ++k) {
-            LAUNCH(c, f32 ? "basis_gradlap_f32" : "basis_gradlap_f64",
-                   launch_basis(dseg + k, 1, segs[k].unit_count, s->spline_lds, f32, c->stream, 0, EXTRA_GRAD_H));
-            LAUNCH(c, f32 ? "nforce_f32" : "nforce_f64", launch_n_force(mode, dseg + k, 1, segs[k].item_count, c->stream));
-        }
+        st = block_loop(
+            c, segs.size(), ovl, f32 ? "basis_gradlap_f32" : "basis_gradlap_f64", f32 ? "nforce_f32" : "nforce_f64",
+            [&](size_t k, hipStream_t q) {
+                return launch_basis(dseg + k, 1, segs[k].unit_count, s->spline_lds, f32, q, 0, EXTRA_GRAD_H);
+            },
+            [&](size_t k) { return launch_n_force(mode, dseg + k, 1, segs[k].item_count, c->stream); });
+        if (st != NAO_OK) return st;
     }
     LAUNCH(c, "force_atoms", launch_force_atoms(s->d_fb.as<double>(), s->d_atom_first.as<int64_t>(), na, Fd, c->stream));
     if (F_space == NAO_MEM_HOST && na > 0)

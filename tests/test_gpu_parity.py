@@ -269,6 +269,46 @@ def test_small_blocks(nao, monkeypatch, overlap):
     c.close()
 
 
+def test_small_blocks_extended_operations(nao, monkeypatch):
+    """The density gradient, the Hamiltonian with a field and with the kinetic term, and the local
+    Pulay forces over blocks of at most 16 MB of basis values: with the overlap (basis values and
+    their extra values in two buffers, basis launches on a second stream) equal to the serial
+    loop up to the order of the FP64 atomics, on two calls in a row, in FP64 and FP32."""
+    from workloads.generate import energy_weighted_for
+    w, B, ref = case("multitile")
+    monkeypatch.setenv("NAO_SCRATCH_MB", "16")
+    a = 0.3 * np.random.default_rng(31).normal(size=(len(w["xyz"]), 3))
+    Q = energy_weighted_for(w, 1)
+    out = {}
+    for overlap in ("1", "0"):
+        monkeypatch.setenv("NAO_OVERLAP", overlap)
+        c = nao.Context(0)
+        c.profile(True)
+        s = nao.build_batches(c, w["basis"], w["xyz"], w["w"], w["max_batch"])
+        for prec in ("fp64", "fp32"):
+            for rep in range(2):
+                say("small blocks, extended operations, overlap", overlap, prec, rep)
+                n, gn = s.update_density_gradient(w["D"], precision=prec)
+                r = (n, gn, s.integrate_h_gga(w["v"], a, precision=prec),
+                     s.integrate_h_ks(w["v"], precision=prec), s.pulay_forces(w["D"], Q, w["v"], precision=prec))
+                if rep == 0:
+                    out[(overlap, prec)] = r
+                else:  # the second call reuses the buffers and events
+                    for x, y in zip(r, out[(overlap, prec)]):
+                        assert rel_max(x, y) <= 1e-13
+        prof = c.profile_read()
+        assert prof["basis_grad_f64"][0] >= 2 * 3  # three or more blocks per call
+        s.close()
+        c.close()
+    for prec in ("fp64", "fp32"):
+        tol = 1e-12  # FP32 tile sums are the same; only the order of the FP64 atomics differs
+        names = ("n", "grad n", "H with a field", "H with the kinetic term", "forces")
+        for nm, x, y in zip(names, out[("1", prec)], out[("0", prec)]):
+            e = rel_max(x, y)
+            say("small blocks, extended operations", prec, nm, "overlap vs serial %.2e" % e)
+            assert e <= tol
+
+
 # Stated error bounds of the reduced-precision modes against the FP64 oracle (normwise max
 # relative error of H, n and N_e); the measured values are printed for the record.
 PREC_TOL = {"fp32": 1e-6, "bf16x3": 3e-5, "bf16x6": 1e-6}
