@@ -269,6 +269,37 @@ def test_small_blocks(nao, monkeypatch, overlap):
     c.close()
 
 
+def test_small_blocks_budget_without_room_for_overlap(nao, monkeypatch):
+    """A budget that holds the system and one basis buffer but not the second: the calls run
+    their blocks serially (no error) and still equal the oracle."""
+    import ctypes
+    w, B, ref = case("multitile")
+    monkeypatch.setenv("NAO_SCRATCH_MB", "16")
+    monkeypatch.setenv("NAO_OVERLAP", "0")
+    probe = nao.Context(0)
+    s = nao.build_batches(probe, w["basis"], w["xyz"], w["w"], w["max_batch"])
+    s.integrate_h(w["v"])
+    s.update_density(w["D"])
+    used, budget = ctypes.c_size_t(), ctypes.c_size_t()
+    assert nao._lib.nao_ctx_memory(probe.handle, ctypes.byref(used), ctypes.byref(budget)) == 0
+    s.close()
+    probe.close()
+    monkeypatch.setenv("NAO_OVERLAP", "1")
+    say("small blocks, budget without room for the second buffer")
+    c = nao.Context(0, hbm_budget=int(used.value) + (1 << 20))
+    c.profile(True)
+    s = nao.build_batches(c, w["basis"], w["xyz"], w["w"], w["max_batch"])
+    for rep in range(2):
+        assert rel_max(s.integrate_h(w["v"]), ref["H"]) <= TOL
+        assert rel_max(s.update_density(w["D"]), ref["n"]) <= TOL
+    assert c.profile_read()["basis_f64"][0] >= 4 * 3  # four calls of three or more blocks
+    used2 = ctypes.c_size_t()
+    assert nao._lib.nao_ctx_memory(c.handle, ctypes.byref(used2), ctypes.byref(budget)) == 0
+    assert used2.value <= budget.value
+    s.close()
+    c.close()
+
+
 def test_small_blocks_extended_operations(nao, monkeypatch):
     """The density gradient, the Hamiltonian with a field and with the kinetic term, and the local
     Pulay forces over blocks of at most 16 MB of basis values: with the overlap (basis values and
