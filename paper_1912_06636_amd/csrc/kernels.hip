@@ -1247,10 +1247,13 @@ __global__ __launch_bounds__(64 * NW) void n_kernel(const DevSeg* __restrict__ s
         if (np <= 0 || m <= 0) continue;
         const int P = (np + 15) >> 4;
         const int J0 = it.tj * TILE;
+        // this wave's 16 output columns hold list entries (the last tile of a unit is padded)
+        const bool col_live = __builtin_amdgcn_readfirstlane(J0 + cb * 16 < m);
         // chunk c covers columns KC c .. KC c + KC - 1: the tiles I <= J, or all tiles for the
         // gradient (T = Phi D over the whole list); the forces walk the list once against D and
-        // once against Q (chunk c + half covers the columns of chunk c)
-        const int half = (FULL ? (m + TILE - 1) / TILE : it.tj + 1) * (TILE / KC);
+        // once against Q (chunk c + half covers the columns of chunk c).  Chunks that start at
+        // or beyond m hold only the zero padding of the basis values and are left out.
+        const int half = min(FULL ? (m + TILE - 1) / TILE * (TILE / KC) : (it.tj + 1) * (TILE / KC), (m + KC - 1) / KC);
         const int n_chunks = FORCE ? 2 * half : half;
         auto col0 = [&](int c) { return KC * (FORCE && c >= half ? c - half : c); };
         const int cjd = J0 + (tid & (TILE - 1));              // this thread's D column in every chunk
@@ -1353,6 +1356,7 @@ __global__ __launch_bounds__(64 * NW) void n_kernel(const DevSeg* __restrict__ s
             stash(0, 0);
             __syncthreads();
             auto mfma_chunk = [&](int buf) {
+                if (!col_live) return;  // this wave's 16 columns lie in the tile's padding
                 if constexpr (SLOT) {
                     // lane group lk reads slots lk + 4 h of its rows; step (h, e) takes column
                     // VPS (lk + 4 h) + e of the chunk
